@@ -1,0 +1,139 @@
+"""CPU oracle for the checkerboard Metropolis sweep of the 2D Ising model.
+
+TEST INFRASTRUCTURE ONLY: only ``tests/``, ``__graft_entry__.smoke()`` and the
+CPU-baseline leg of ``bench.py`` may import this package.  The product path
+(``paper_1007_3726_amd``) never imports it and shares no code with it.
+
+Thin ctypes wrapper over ``ising_oracle.c``; every function below forwards to
+the C routine of the same role, whose comments cite the paper's sections and
+equations.
+"""
+import ctypes
+import math
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_lib = None
+
+
+def lib():
+    """Load (building first if missing or stale) the oracle shared library."""
+    global _lib
+    if _lib is None:
+        path = _build.build(force=False)
+        L = ctypes.CDLL(path)
+        u32, i32, i64, u64 = ctypes.c_uint32, ctypes.c_int, ctypes.c_int64, ctypes.c_uint64
+        p8 = ctypes.POINTER(ctypes.c_int8)
+        p64 = ctypes.POINTER(ctypes.c_int64)
+        pu32 = ctypes.POINTER(ctypes.c_uint32)
+        L.oracle_philox4x32_10.argtypes = [pu32, pu32, pu32]
+        L.oracle_philox4x32_10.restype = None
+        L.oracle_threshold.argtypes = [ctypes.c_double, i32]
+        L.oracle_threshold.restype = u32
+        L.oracle_uniform.argtypes = [u64, u32, u32, u32, i64, i64, i64]
+        L.oracle_uniform.restype = u32
+        L.oracle_accept.argtypes = [i32, i32, i32, i32, i32, u32, u32, u32]
+        L.oracle_accept.restype = i32
+        L.oracle_init.argtypes = [i64, u64, u32, i32, p8]
+        L.oracle_init.restype = None
+        L.oracle_measure.argtypes = [i64, p8, p64, p64]
+        L.oracle_measure.restype = None
+        L.oracle_sweeps.argtypes = [i64, u32, u32, u64, u32, u32, i64, p8, p64]
+        L.oracle_sweeps.restype = None
+        L.oracle_window.argtypes = [i64, u32, u32, u64, u32, i32, u32, i64, i64, i64, i64, i64, p8]
+        L.oracle_window.restype = i32
+        L.oracle_get_threads.argtypes = []
+        L.oracle_get_threads.restype = i32
+        L.oracle_set_threads.argtypes = [i32]
+        L.oracle_set_threads.restype = None
+        _lib = L
+    return _lib
+
+
+def _p8(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int8))
+
+
+def _p64(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+
+
+def philox4x32_10(ctr, key):
+    """Philox4x32-10 block: 4 counter words, 2 key words -> 4 output words."""
+    c = (ctypes.c_uint32 * 4)(*[int(v) & 0xFFFFFFFF for v in ctr])
+    k = (ctypes.c_uint32 * 2)(*[int(v) & 0xFFFFFFFF for v in key])
+    o = (ctypes.c_uint32 * 4)()
+    lib().oracle_philox4x32_10(c, k, o)
+    return [int(o[i]) for i in range(4)]
+
+
+def check_beta(beta: float) -> None:
+    if math.isnan(beta) or beta < 0:
+        raise ValueError("beta must be >= 0 (or +inf)")
+
+
+def thresholds(beta: float):
+    """(t4, t8): integer Metropolis thresholds for dE = 4 and dE = 8."""
+    check_beta(beta)
+    return int(lib().oracle_threshold(beta, 4)), int(lib().oracle_threshold(beta, 8))
+
+
+def uniform(seed, stream_id, phase, t, L, x, y) -> int:
+    return int(lib().oracle_uniform(seed, stream_id, phase, t, L, x, y))
+
+
+def accept(s, n1, n2, n3, n4, u, t4, t8) -> int:
+    return int(lib().oracle_accept(s, n1, n2, n3, n4, u, t4, t8))
+
+
+def init(L: int, seed: int, stream_id: int, init_kind: int) -> np.ndarray:
+    s = np.empty((L, L), dtype=np.int8)
+    lib().oracle_init(L, seed, stream_id, init_kind, _p8(s))
+    return s
+
+
+def measure(s: np.ndarray):
+    s = np.ascontiguousarray(s, dtype=np.int8)
+    E = ctypes.c_int64()
+    M = ctypes.c_int64()
+    lib().oracle_measure(s.shape[0], _p8(s), ctypes.byref(E), ctypes.byref(M))
+    return int(E.value), int(M.value)
+
+
+def sweeps(s: np.ndarray, beta: float, seed: int, stream_id: int, t0: int, n: int,
+           record: bool = True):
+    """Run n sweeps in place on int8 spins s (L x L); returns EM[n, 2] or None."""
+    assert s.dtype == np.int8 and s.flags.c_contiguous and s.shape[0] == s.shape[1]
+    t4, t8 = thresholds(beta)
+    EM = np.zeros((n, 2), dtype=np.int64) if record else None
+    lib().oracle_sweeps(s.shape[0], t4, t8, seed, stream_id, t0, n, _p8(s),
+                        _p64(EM) if record else None)
+    return EM
+
+
+def run(L: int, beta: float, seed: int, stream_id: int, init_kind: int, n: int):
+    """Fresh lattice, n sweeps from t = 0: returns (spins, EM[n, 2])."""
+    s = init(L, seed, stream_id, init_kind)
+    EM = sweeps(s, beta, seed, stream_id, 0, n)
+    return s, EM
+
+
+def window(L, beta, seed, stream_id, init_kind, t0, n, x0, y0, w, h) -> np.ndarray:
+    """Exact w x h window at (x0, y0) after n sweeps from a fresh init (light cone)."""
+    t4, t8 = thresholds(beta)
+    out = np.empty((h, w), dtype=np.int8)
+    rc = lib().oracle_window(L, t4, t8, seed, stream_id, init_kind, t0, n, x0, y0, w, h, _p8(out))
+    if rc != 0:
+        raise ValueError("window plus light-cone margin does not fit in the lattice")
+    return out
+
+
+def set_threads(n: int) -> None:
+    lib().oracle_set_threads(n)
+
+
+def get_threads() -> int:
+    return int(lib().oracle_get_threads())

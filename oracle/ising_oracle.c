@@ -1,0 +1,308 @@
+/*
+ * Oracle for the checkerboard Metropolis sweep of the 2D Ising model.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the slow, plain, byte-per-spin
+ * reference that the HIP path is checked against.  Only the tests, the
+ * smoke check and the CPU-baseline leg of the benchmark may load it; the
+ * product library never links, loads or calls it, and it shares no code,
+ * header, table or helper with the HIP sources.
+ *
+ * What it computes (B. Block, P. Virnau, T. Preis, "Multi-GPU accelerated
+ * multi-spin Monte Carlo simulations of the 2D Ising model"):
+ *   - Section 3, Eq. (1): H = -J sum_<ij> S_i S_j - H sum_i S_i on an L x L
+ *     square lattice with periodic boundaries; here J = 1, k_B = 1, field 0.
+ *   - Section 3: Metropolis acceptance W = exp(-dH/T) for dH > 0, else 1;
+ *     the two possible factors (dH = 4J and 8J) are computed on the host
+ *     once per temperature.
+ *   - Section 3: checkerboard update, all sites of one colour (step A),
+ *     then all sites of the other colour (step B), B strictly after A.
+ *   - Section 4, Eq. (3): a move is accepted when a uniform r in [0,1) is
+ *     strictly below the Boltzmann factor.  Here r is a 32-bit integer u and
+ *     the factor is the integer threshold floor(exp(-dH/T) * 2^32), clamped
+ *     to 2^32 - 1, so "r < exp(-dH/T)" becomes "u < threshold".
+ *
+ * Readings of points the paper leaves open (listed in the design doc):
+ *   - colour of site (x, y) is (x + y) mod 2; colour 0 is updated first;
+ *   - the uniforms come from Philox4x32-10 (Salmon, Moraes, Dror, Shaw,
+ *     "Parallel random numbers: as easy as 1, 2, 3", SC'11), keyed by
+ *     (seed, stream id, sweep, phase, site) as in oracle_uniform() below;
+ *     the paper's own generator is a per-thread LCG (section 5.3);
+ *   - L even and >= 4; spins are +1/-1 stored one int8 per site, row-major
+ *     [y][x]; a set bit in a packed layout means +1 (section 5.2);
+ *   - energy E and magnetisation M are exact int64 sums measured after each
+ *     full sweep.
+ *
+ * Every function is written for clarity, not speed: one site at a time.
+ * The only parallelism is OpenMP over rows inside one colour step, which is
+ * legal because sites of one colour do not interact (section 3).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* ------------------------------------------------------------------ */
+/* Philox4x32-10 (Salmon et al., SC'11): ten rounds of                 */
+/*   (hi0,lo0) = M0 * x0, (hi1,lo1) = M1 * x2,                          */
+/*   x <- (hi1 ^ x1 ^ k0, lo1, hi0 ^ x3 ^ k1, lo0),                     */
+/* with the key bumped by the Weyl constants between rounds.           */
+/* ------------------------------------------------------------------ */
+void oracle_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+    const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+    uint32_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += W0;
+            k1 += W1;
+        }
+        uint64_t p0 = (uint64_t)M0 * (uint64_t)x0;
+        uint64_t p1 = (uint64_t)M1 * (uint64_t)x2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        x0 = hi1 ^ x1 ^ k0;
+        x1 = lo1;
+        x2 = hi0 ^ x3 ^ k1;
+        x3 = lo0;
+    }
+    out[0] = x0;
+    out[1] = x1;
+    out[2] = x2;
+    out[3] = x3;
+}
+
+/* ------------------------------------------------------------------ */
+/* Integer Metropolis threshold for an uphill move of size dE          */
+/* (section 3: W = exp(-dE/T), precomputed on the host per T;         */
+/*  section 4, Eq. (3): accept when r < W).                            */
+/* Returns floor(exp(-beta*dE) * 2^32), clamped to 2^32 - 1.          */
+/* beta must be >= 0 (may be +inf); the caller checks this.            */
+/* ------------------------------------------------------------------ */
+uint32_t oracle_threshold(double beta, int dE)
+{
+    double w = exp(-beta * (double)dE);
+    double scaled = floor(ldexp(w, 32));
+    if (scaled >= 4294967295.0)
+        return 0xFFFFFFFFu;
+    if (scaled <= 0.0)
+        return 0u;
+    return (uint32_t)scaled;
+}
+
+/* ------------------------------------------------------------------ */
+/* The uniform used at site (x, y) in sweep t for a given phase.       */
+/* Keying (the build's reading; the paper's LCG is replaced):          */
+/*   colour-local index i = y * (L/2) + floor(x/2),                    */
+/*   group g = floor(i / 4), lane j = i mod 4,                          */
+/*   key = (lo32(seed), hi32(seed)),                                    */
+/*   counter = (lo32(g), hi32(g), t, (stream_id << 2) | phase),         */
+/*   u = Philox4x32-10(key, counter)[j].                                */
+/* phase 0/1: update of colour 0/1 in sweep t; phase 2/3: hot start    */
+/* of colour 0/1 sites (t = 0).                                        */
+/* ------------------------------------------------------------------ */
+uint32_t oracle_uniform(uint64_t seed, uint32_t stream_id, uint32_t phase,
+                        uint32_t t, int64_t L, int64_t x, int64_t y)
+{
+    uint64_t i = (uint64_t)y * (uint64_t)(L / 2) + (uint64_t)(x / 2);
+    uint64_t g = i >> 2;
+    uint32_t j = (uint32_t)(i & 3u);
+    uint32_t ctr[4] = {(uint32_t)g, (uint32_t)(g >> 32), t, (stream_id << 2) | phase};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t out[4];
+    oracle_philox4x32_10(ctr, key, out);
+    return out[j];
+}
+
+/* ------------------------------------------------------------------ */
+/* Metropolis decision for one site (section 3), written with the      */
+/* energy change of Eq. (1): flipping s changes H by                    */
+/*   dE = 2 J s (n1 + n2 + n3 + n4),  J = 1.                            */
+/* dE <= 0: always accepted; dE = 4: accepted iff u < t4;              */
+/* dE = 8: accepted iff u < t8.  Returns 1 to flip, 0 to keep.         */
+/* ------------------------------------------------------------------ */
+int oracle_accept(int s, int n1, int n2, int n3, int n4,
+                  uint32_t u, uint32_t t4, uint32_t t8)
+{
+    int dE = 2 * s * (n1 + n2 + n3 + n4);
+    if (dE <= 0)
+        return 1;
+    if (dE == 4)
+        return u < t4;
+    /* dE == 8 */
+    return u < t8;
+}
+
+static inline int64_t wrap(int64_t a, int64_t L)
+{
+    a %= L;
+    return a < 0 ? a + L : a;
+}
+
+/* ------------------------------------------------------------------ */
+/* Initial state.  init 0: all +1; init 1: all -1; init 2: hot start,  */
+/* s = +1 iff the site's phase-(2 + colour) uniform at t = 0 is below  */
+/* 2^31 (probability 1/2).                                              */
+/* ------------------------------------------------------------------ */
+void oracle_init(int64_t L, uint64_t seed, uint32_t stream_id, int init, int8_t *s)
+{
+    for (int64_t y = 0; y < L; ++y)
+        for (int64_t x = 0; x < L; ++x) {
+            int8_t v;
+            if (init == 0)
+                v = 1;
+            else if (init == 1)
+                v = -1;
+            else {
+                uint32_t colour = (uint32_t)((x + y) & 1);
+                uint32_t u = oracle_uniform(seed, stream_id, 2u + colour, 0u, L, x, y);
+                v = (u < 0x80000000u) ? 1 : -1;
+            }
+            s[y * L + x] = v;
+        }
+}
+
+/* ------------------------------------------------------------------ */
+/* Energy and magnetisation of a configuration, Eq. (1) with J = 1 and  */
+/* no field: E = -sum_{x,y} s(x,y) [s(x+1,y) + s(x,y+1)] (each of the  */
+/* 2 L^2 bonds once), M = sum s.                                         */
+/* ------------------------------------------------------------------ */
+void oracle_measure(int64_t L, const int8_t *s, int64_t *E, int64_t *M)
+{
+    int64_t e = 0, m = 0;
+    for (int64_t y = 0; y < L; ++y)
+        for (int64_t x = 0; x < L; ++x) {
+            int64_t v = s[y * L + x];
+            int64_t right = s[y * L + wrap(x + 1, L)];
+            int64_t down = s[wrap(y + 1, L) * L + x];
+            e -= v * (right + down);
+            m += v;
+        }
+    *E = e;
+    *M = m;
+}
+
+/* One colour step (section 3, step A or B) over the sites of `colour`. */
+static void colour_step(int64_t L, uint32_t t4, uint32_t t8, uint64_t seed,
+                        uint32_t stream_id, uint32_t t, int colour, int8_t *s)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t y = 0; y < L; ++y) {
+        for (int64_t x = (y + colour) & 1; x < L; x += 2) {
+            int v = s[y * L + x];
+            int n1 = s[y * L + wrap(x - 1, L)];
+            int n2 = s[y * L + wrap(x + 1, L)];
+            int n3 = s[wrap(y - 1, L) * L + x];
+            int n4 = s[wrap(y + 1, L) * L + x];
+            uint32_t u = oracle_uniform(seed, stream_id, (uint32_t)colour, t, L, x, y);
+            if (oracle_accept(v, n1, n2, n3, n4, u, t4, t8))
+                s[y * L + x] = (int8_t)(-v);
+        }
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* n full sweeps starting at sweep counter t0: for each sweep t, colour */
+/* 0 then colour 1 (section 3), then (E_t, M_t) into EM[2k], EM[2k+1]  */
+/* (EM may be NULL).                                                    */
+/* ------------------------------------------------------------------ */
+void oracle_sweeps(int64_t L, uint32_t t4, uint32_t t8, uint64_t seed, uint32_t stream_id,
+                   uint32_t t0, int64_t n, int8_t *s, int64_t *EM)
+{
+    for (int64_t k = 0; k < n; ++k) {
+        uint32_t t = t0 + (uint32_t)k;
+        colour_step(L, t4, t8, seed, stream_id, t, 0, s);
+        colour_step(L, t4, t8, seed, stream_id, t, 1, s);
+        if (EM)
+            oracle_measure(L, s, &EM[2 * k], &EM[2 * k + 1]);
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* Light-cone window.  After n sweeps a site depends only on the       */
+/* initial spins and uniforms within Manhattan distance 2n (one site   */
+/* per colour step).  This simulates the patch of global coordinates   */
+/* [x0 - m, x0 + w + m) x [y0 - m, y0 + h + m) (periodic in L) with     */
+/* m = 2n + 1, keeping the outermost ring frozen, and returns the inner */
+/* w x h window, which then equals the full-lattice result exactly.     */
+/* The uniforms are keyed by global coordinates.  Requires w + 2m <= L  */
+/* and h + 2m <= L (otherwise run oracle_sweeps on the whole lattice).  */
+/* Returns 0 on success, -1 on a size error.                            */
+/* ------------------------------------------------------------------ */
+int oracle_window(int64_t L, uint32_t t4, uint32_t t8, uint64_t seed, uint32_t stream_id,
+                  int init, uint32_t t0, int64_t n, int64_t x0, int64_t y0,
+                  int64_t w, int64_t h, int8_t *out)
+{
+    int64_t m = 2 * n + 1;
+    int64_t pw = w + 2 * m, ph = h + 2 * m;
+    if (pw > L || ph > L || w <= 0 || h <= 0)
+        return -1;
+    int8_t *p = (int8_t *)malloc((size_t)(pw * ph));
+    if (!p)
+        return -1;
+    /* initial state at global coordinates */
+    for (int64_t j = 0; j < ph; ++j)
+        for (int64_t i = 0; i < pw; ++i) {
+            int64_t gx = wrap(x0 - m + i, L), gy = wrap(y0 - m + j, L);
+            int8_t v;
+            if (init == 0)
+                v = 1;
+            else if (init == 1)
+                v = -1;
+            else {
+                uint32_t colour = (uint32_t)((gx + gy) & 1);
+                uint32_t u = oracle_uniform(seed, stream_id, 2u + colour, 0u, L, gx, gy);
+                v = (u < 0x80000000u) ? 1 : -1;
+            }
+            p[j * pw + i] = v;
+        }
+    for (int64_t k = 0; k < n; ++k) {
+        uint32_t t = t0 + (uint32_t)k;
+        for (int colour = 0; colour < 2; ++colour) {
+#pragma omp parallel for schedule(static)
+            for (int64_t j = 1; j < ph - 1; ++j) {
+                for (int64_t i = 1; i < pw - 1; ++i) {
+                    int64_t gx = wrap(x0 - m + i, L), gy = wrap(y0 - m + j, L);
+                    if (((gx + gy) & 1) != colour)
+                        continue;
+                    int v = p[j * pw + i];
+                    int n1 = p[j * pw + i - 1];
+                    int n2 = p[j * pw + i + 1];
+                    int n3 = p[(j - 1) * pw + i];
+                    int n4 = p[(j + 1) * pw + i];
+                    uint32_t u = oracle_uniform(seed, stream_id, (uint32_t)colour, t, L, gx, gy);
+                    if (oracle_accept(v, n1, n2, n3, n4, u, t4, t8))
+                        p[j * pw + i] = (int8_t)(-v);
+                }
+            }
+        }
+    }
+    for (int64_t j = 0; j < h; ++j)
+        memcpy(out + j * w, p + (j + m) * pw + m, (size_t)w);
+    free(p);
+    return 0;
+}
+
+/* Number of OpenMP threads the oracle uses (1 when built without it). */
+int oracle_get_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+void oracle_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0)
+        omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
