@@ -1,0 +1,223 @@
+/*
+ * ising.h - C ABI of the MI355X (gfx950) multi-spin-coded checkerboard
+ * Metropolis sweep of the 2D ferromagnetic Ising model.
+ *
+ * Model (B. Block, P. Virnau, T. Preis, "Multi-GPU accelerated multi-spin
+ * Monte Carlo simulations of the 2D Ising model"):
+ *   - Section 3, Eq. (1): H = -J sum_<ij> S_i S_j on an L x L square lattice
+ *     with periodic boundaries, J = 1, k_B = 1, no field.
+ *   - Section 3: Metropolis acceptance exp(-dH/T) for dH > 0, else 1; the two
+ *     possible factors (dH = 4 and 8) are precomputed on the host per
+ *     temperature (ising_set_beta).
+ *   - Section 3: checkerboard sweep; all sites of colour 0 ((x + y) even),
+ *     then all sites of colour 1.
+ *   - Section 4, Eqs. (3)-(5): multi-spin coding; a site flips when
+ *     (number of anti-aligned neighbours) + [u < t4] + [u < t8] >= 2, with
+ *     u a 32-bit uniform and t4, t8 the integer thresholds below.
+ *   - Section 5.2: one bit per spin, a set bit meaning +1.
+ *
+ * Uniforms: Philox4x32-10 (Salmon et al., SC'11).  For site (x, y) the
+ * colour-local index is i = y*(L/2) + x/2, the block is g = i/4 and the
+ * output word is i mod 4; key = (lo32(seed), hi32(seed)); counter =
+ * (lo32(g), hi32(g), sweep, (stream_id << 2) | phase) with phase 0/1 for
+ * the colour-0/1 update and 2/3 for the hot start of colour-0/1 sites.
+ * Results are therefore independent of the device layout, the launch shape,
+ * batching and co-scheduling: a lattice is a pure function of
+ * (L, beta history, seed, stream_id, init, sweep count).
+ *
+ * Conventions for every entry point:
+ *   - Returns an ising_status (int32).  No C++ exception crosses the ABI.
+ *     On failure ising_last_error() gives a thread-local message.
+ *   - Device memory is always owned by the caller (e.g. a torch uint8 tensor
+ *     on the GPU); the library never frees it.  Host buffers are owned by
+ *     the caller.
+ *   - A handle is not thread-safe; distinct handles are independent.
+ *   - Work is enqueued asynchronously on the HIP stream given at creation
+ *     (NULL = the legacy default stream) unless the function says it
+ *     synchronises.
+ *
+ * Device layout of a lattice (ising_lattice_bytes bytes, 256-B aligned):
+ *   plane 0 (colour 0) then plane 1 (colour 1), each L rows of W uint64
+ *   words, W = ceil((L/2)/64).  Bit b of word w in row y of plane c holds
+ *   the site x = 2*(64*w + b) + ((y + c) & 1); padding bits are zero.
+ *   A 256-byte scratch area follows the planes.
+ */
+#ifndef ISING_H
+#define ISING_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#if defined(__GNUC__) || defined(__clang__)
+#define ISING_API __attribute__((visibility("default")))
+#else
+#define ISING_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t ising_status;
+#define ISING_OK 0
+#define ISING_AGAIN 1         /* ising_poll: request not finished yet */
+#define ISING_EINVAL (-1)     /* bad argument (null pointer, bad size, bad beta, ...) */
+#define ISING_ENOMEM (-2)     /* caller buffer or arena too small */
+#define ISING_EDEVICE (-3)    /* a HIP call failed */
+#define ISING_ENOTFOUND (-4)  /* unknown ticket */
+#define ISING_ERANGE (-5)     /* the sweep counter would pass 2^32 - 1 */
+
+#define ISING_INIT_COLD_UP 0   /* all spins +1 */
+#define ISING_INIT_COLD_DOWN 1 /* all spins -1 */
+#define ISING_INIT_HOT 2       /* each spin +1 iff its phase-(2+colour) uniform < 2^31 */
+
+typedef struct ising_lattice ising_t;
+typedef struct ising_server ising_server_t;
+
+/* Thread-local text of the last failure in this thread ("" if none). */
+ISING_API const char *ising_last_error(void);
+
+/* Library version string. */
+ISING_API const char *ising_version(void);
+
+/* Device bytes a lattice of side L needs (planes + 256 B scratch); 0 if L
+ * is invalid (odd, < 4 or > 2^21). */
+ISING_API size_t ising_lattice_bytes(int64_t L);
+
+/*
+ * Create a lattice of side L (even, 4 <= L <= 2^21) in the caller's device
+ * buffer dev_buf (at least ising_lattice_bytes(L) bytes, 256-B aligned) and
+ * enqueue its initialisation (init = ISING_INIT_*) on hip_stream.  seed is
+ * the Philox key; stream_id (< 2^30) separates independent chains with the
+ * same seed.  The sweep counter starts at 0.  No beta is set yet.
+ * Errors: EINVAL (bad L, init, stream_id, alignment or null pointer),
+ * ENOMEM (dev_bytes too small), EDEVICE.
+ */
+ISING_API ising_status ising_create(int64_t L, uint64_t seed, uint32_t stream_id, int32_t init,
+                          void *dev_buf, size_t dev_bytes, void *hip_stream, ising_t **out);
+
+/* Release the handle (never frees dev_buf).  NULL is accepted. */
+ISING_API ising_status ising_destroy(ising_t *h);
+
+/*
+ * Set the inverse temperature (section 3: Boltzmann factors precomputed on
+ * the host per temperature).  beta >= 0, finite or +inf; NaN or negative
+ * gives EINVAL.  Thresholds: t4 = min(floor(exp(-4 beta) 2^32), 2^32 - 1),
+ * t8 = min(floor(exp(-8 beta) 2^32), 2^32 - 1) (binary64 exp).
+ */
+ISING_API ising_status ising_set_beta(ising_t *h, double beta);
+
+/* t[0] = t4, t[1] = t8 for the current beta (EINVAL before set_beta). */
+ISING_API ising_status ising_get_thresholds(const ising_t *h, uint32_t t[2]);
+
+/*
+ * Enqueue n >= 0 full sweeps (colour 0 then colour 1, section 3) with sweep
+ * counters h.sweep ... h.sweep + n - 1, then advance h.sweep by n.
+ * If dev_EM is not NULL it is a device array of n x 2 int64: after sweep k
+ * it holds E_k = -sum_<ij> S_i S_j and M_k = sum_i S_i (exact).
+ * Errors: EINVAL (no beta set, n < 0), ERANGE (counter overflow), EDEVICE.
+ */
+ISING_API ising_status ising_sweep(ising_t *h, int64_t n, int64_t *dev_EM);
+
+/* E and M of the current state into host *E, *M.  Synchronises the stream. */
+ISING_API ising_status ising_measure(ising_t *h, int64_t *E, int64_t *M);
+
+/* Copy all spins to host (L*L int8, +1/-1, row-major [y][x]).  Synchronises. */
+ISING_API ising_status ising_get_spins(ising_t *h, int8_t *host);
+
+/* Overwrite all spins from host (L*L int8, each +1 or -1, else EINVAL).
+ * Synchronises.  The sweep counter is unchanged. */
+ISING_API ising_status ising_set_spins(ising_t *h, const int8_t *host);
+
+/* Copy the w x h window with top-left (x0, y0) (periodic, 0 <= x0, y0 < L,
+ * 1 <= w, h <= L) to host (h rows of w int8).  Synchronises. */
+ISING_API ising_status ising_get_window(ising_t *h, int64_t x0, int64_t y0, int64_t w, int64_t hgt,
+                              int8_t *host);
+
+/* Checkpoint/resume of the sweep counter (< 2^32). */
+ISING_API ising_status ising_get_sweep(const ising_t *h, uint64_t *t);
+ISING_API ising_status ising_set_sweep(ising_t *h, uint64_t t);
+
+/* Side L and device address of the lattice planes (for tests). */
+ISING_API ising_status ising_get_info(const ising_t *h, int64_t *L, int64_t *words_per_row, void **planes);
+
+/*
+ * Batched sweeps: enqueue n sweeps on each of the `count` handles (all
+ * created on the same device and stream, each with a beta set) in one
+ * persistent fused kernel launch, equivalent bit for bit to calling
+ * ising_sweep(hs[i], n, dev_EM[i]) on each.  dev_EM may be NULL or hold
+ * NULL entries.  Each handle's counter advances by n.
+ * Errors: EINVAL, ERANGE, EDEVICE.
+ */
+ISING_API ising_status ising_multi_sweep(ising_t *const *hs, int32_t count, int64_t n,
+                               int64_t *const *dev_EM);
+
+/* ---------------------------------------------------------------- */
+/* Served mode: continuous batching of independent simulations.      */
+/* ---------------------------------------------------------------- */
+
+#define ISING_REQ_RECORD_SERIES 1u /* copy the per-sweep (E, M) series to EM_series */
+#define ISING_REQ_RETURN_SPINS 2u  /* copy the final spins to spins_out */
+
+typedef struct {
+    int64_t L;           /* even, >= 4 */
+    double beta;         /* >= 0 or +inf */
+    uint64_t seed;
+    uint32_t stream_id;  /* < 2^30 */
+    int32_t init;        /* ISING_INIT_* */
+    int64_t n_sweeps;    /* >= 1 */
+    int64_t n_discard;   /* sweeps excluded from the moment sums */
+    uint32_t flags;      /* ISING_REQ_* */
+    int64_t *EM_series;  /* caller-owned host buffer of n_sweeps x 2, or NULL */
+    int8_t *spins_out;   /* caller-owned host buffer of L*L, or NULL */
+} ising_request;
+
+typedef struct {
+    uint64_t ticket;
+    int32_t status;       /* ISING_OK when done, ISING_AGAIN while running */
+    int64_t E_final, M_final;
+    uint64_t sweeps_done;
+    double sum_M2, sum_M4; /* exact integer sums over kept sweeps, rounded to double */
+    int64_t n_kept;
+    double t_arrive, t_admit, t_done; /* seconds on the host monotonic clock */
+} ising_result;
+
+/*
+ * A server owns nothing on the device except what it carves from the
+ * caller's arena (dev_arena, arena_bytes = the HBM budget).  Requests are
+ * admitted in FIFO order whenever their lattice fits in the free arena;
+ * every quantum runs quantum_sweeps sweeps on all admitted lattices in one
+ * fused launch (continuous batching).  Results do not depend on the mix:
+ * each lattice's uniforms are keyed by its own (seed, stream_id, sweep).
+ */
+ISING_API ising_status ising_server_create(void *dev_arena, size_t arena_bytes, void *hip_stream,
+                                 int32_t quantum_sweeps, ising_server_t **out);
+
+/* Queue n requests; tickets_out[i] receives each ticket.  Requests larger
+ * than the whole arena are rejected (ENOMEM) without queueing any. */
+ISING_API ising_status ising_batch_submit(ising_server_t *s, const ising_request *reqs, int32_t n,
+                                uint64_t *tickets_out);
+
+/* Advance the server by one quantum (admit, run, retire).  Returns AGAIN
+ * while work remains, OK when idle. */
+ISING_API ising_status ising_server_step(ising_server_t *s);
+
+/* Result of a ticket: OK (done, *out filled, ticket released), AGAIN
+ * (queued or running; out->status = AGAIN), ENOTFOUND. */
+ISING_API ising_status ising_poll(ising_server_t *s, uint64_t ticket, ising_result *out);
+
+/* Fail the given quantum index (host-side fault injection for tests): the
+ * quantum's work is discarded and re-run from the last committed state. */
+ISING_API ising_status ising_server_inject_fault(ising_server_t *s, int64_t quantum_index);
+
+/* Counters: [0] quanta run, [1] requests admitted, [2] requests done,
+ * [3] bytes in use, [4] peak bytes in use, [5] faults recovered. */
+ISING_API ising_status ising_server_stats(const ising_server_t *s, int64_t out[6]);
+
+ISING_API ising_status ising_server_destroy(ising_server_t *s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ISING_H */

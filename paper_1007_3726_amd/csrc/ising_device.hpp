@@ -1,0 +1,168 @@
+// Device building blocks of the checkerboard sweep on colour-packed words.
+//
+// Layout: plane c holds the sites of colour c ((x + y) mod 2 == c); row y of
+// a plane is W uint64 words; bit b of word w is the colour-local site
+// k = 64*w + b, i.e. x = 2*k + ((y + c) & 1).  A set bit is spin +1
+// (section 5.2 of the paper).  Padding bits past L/2 are always zero.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ising {
+
+// Philox4x32-10 constants (Salmon et al., SC'11).
+constexpr uint32_t kM0 = 0xD2511F53u;
+constexpr uint32_t kM1 = 0xCD9E8D57u;
+constexpr uint32_t kW0 = 0x9E3779B9u;
+constexpr uint32_t kW1 = 0xBB67AE85u;
+
+// a ^ b ^ c in one VALU op (gfx950 BITOP3, truth table 0x96).
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+  return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
+// One Philox4x32-10 block.  Each round is two 32x32->64 multiplies
+// (v_mad_u64_u32, full rate on gfx950) and two three-input XORs; the key
+// schedule is wave-uniform and lives in SGPRs.
+__device__ __forceinline__ void philox4x32_10(uint32_t& x0, uint32_t& x1, uint32_t& x2,
+                                              uint32_t& x3, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t p0 = (uint64_t)kM0 * x0;
+    const uint64_t p1 = (uint64_t)kM1 * x2;
+    const uint32_t y0 = xor3((uint32_t)(p1 >> 32), x1, k0);
+    const uint32_t y2 = xor3((uint32_t)(p0 >> 32), x3, k1);
+    x1 = (uint32_t)p1;
+    x3 = (uint32_t)p0;
+    x0 = y0;
+    x2 = y2;
+    k0 += kW0;
+    k1 += kW1;
+  }
+}
+
+// Geometry of one lattice as the kernels see it.
+struct Geom {
+  int64_t L;        // side
+  int32_t W;        // words per colour-row
+  int32_t nb_last;  // valid bits in the last word of a row (1..64)
+  int64_t L8;       // L / 8 when L % 8 == 0 (Philox blocks per colour-row)
+  int64_t half;     // L / 2
+};
+
+__device__ __forceinline__ uint64_t low_mask(int nbits) {
+  return nbits >= 64 ? ~0ull : ((1ull << nbits) - 1ull);
+}
+
+// Neighbour words of word (y, w) of colour c, read from the other plane `o`
+// (row stride W).  n0: same colour-local index in row y; n1: the horizontal
+// partner (left if (y + c) even, right otherwise), with the periodic wrap
+// of a possibly partial last word; n2/n3: rows y-1 and y+1 (periodic).
+struct Nbr {
+  uint64_t n0, n1, n2, n3;
+};
+
+template <typename Ptr>
+__device__ __forceinline__ Nbr gather(Ptr o, const Geom& g, int c, int64_t y, int32_t w) {
+  const int64_t W = g.W;
+  const int64_t ym = (y == 0) ? g.L - 1 : y - 1;
+  const int64_t yp = (y == g.L - 1) ? 0 : y + 1;
+  const auto row = o + y * W;
+  Nbr n;
+  n.n0 = row[w];
+  n.n2 = o[ym * W + w];
+  n.n3 = o[yp * W + w];
+  if (((y + c) & 1) == 0) {
+    // left partner: site k-1; k = 0 wraps to the last valid site of the row
+    const uint64_t carry =
+        (w > 0) ? (row[w - 1] >> 63) : ((row[W - 1] >> (g.nb_last - 1)) & 1ull);
+    n.n1 = (n.n0 << 1) | carry;
+  } else {
+    // right partner: site k+1; the last valid site wraps to k = 0
+    if (w < g.W - 1)
+      n.n1 = (n.n0 >> 1) | (row[w + 1] << 63);
+    else
+      n.n1 = (n.n0 >> 1) | ((row[0] & 1ull) << (g.nb_last - 1));
+  }
+  return n;
+}
+
+// Bit-sliced Metropolis decision for 64 sites (section 4, Eqs. (4)-(5)).
+// a_i = s ^ n_i marks anti-aligned neighbours; with k = sum a_i the site
+// flips iff k + [u < t4] + [u < t8] >= 2.  Since t8 <= t4, [u < t8] implies
+// [u < t4], so flip = (k >= 2) | ((k >= 1) & r4) | r8.
+__device__ __forceinline__ uint64_t flip_mask(uint64_t s, const Nbr& n, uint64_t r4, uint64_t r8) {
+  const uint64_t a0 = s ^ n.n0, a1 = s ^ n.n1, a2 = s ^ n.n2, a3 = s ^ n.n3;
+  const uint64_t x01 = a0 ^ a1, x23 = a2 ^ a3;
+  const uint64_t ge2 = (a0 & a1) | (a2 & a3) | (x01 & x23);
+  const uint64_t any = a0 | a1 | a2 | a3;
+  return ge2 | (any & r4) | r8;
+}
+
+// Insert the comparison results of one Philox block (4 consecutive sites,
+// starting at bit 4q of a 32-bit half) into the r4/r8 halves.
+__device__ __forceinline__ void insert4(uint32_t& r4, uint32_t& r8, int base, uint32_t x0,
+                                        uint32_t x1, uint32_t x2, uint32_t x3, uint32_t t4,
+                                        uint32_t t8) {
+  r4 |= ((x0 < t4) ? (1u << base) : 0u) | ((x1 < t4) ? (2u << base) : 0u) |
+        ((x2 < t4) ? (4u << base) : 0u) | ((x3 < t4) ? (8u << base) : 0u);
+  r8 |= ((x0 < t8) ? (1u << base) : 0u) | ((x1 < t8) ? (2u << base) : 0u) |
+        ((x2 < t8) ? (4u << base) : 0u) | ((x3 < t8) ? (8u << base) : 0u);
+}
+
+// Uniform comparison masks for word (y, w) when L % 8 == 0: the word's
+// sites are Philox blocks g0 + q, q < nq, with g0 = y*L/8 + 16*w, and
+// block q covers bits 4q..4q+3.  rA = [u < tA], rB = [u < tB] per site.
+__device__ __forceinline__ void masks_aligned(const Geom& g, int64_t y, int32_t w, uint32_t k0,
+                                              uint32_t k1, uint32_t t, uint32_t ctr3, uint32_t tA,
+                                              uint32_t tB, uint64_t& rA, uint64_t& rB) {
+  const int nq = (w == g.W - 1) ? (g.nb_last >> 2) : 16;
+  const uint64_t g0 = (uint64_t)y * (uint64_t)g.L8 + 16ull * (uint64_t)w;
+  uint32_t a_lo = 0, a_hi = 0, b_lo = 0, b_hi = 0;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    if (q < nq) {
+      const uint64_t gq = g0 + (uint64_t)q;
+      uint32_t x0 = (uint32_t)gq, x1 = (uint32_t)(gq >> 32), x2 = t, x3 = ctr3;
+      philox4x32_10(x0, x1, x2, x3, k0, k1);
+      if (q < 8)
+        insert4(a_lo, b_lo, 4 * q, x0, x1, x2, x3, tA, tB);
+      else
+        insert4(a_hi, b_hi, 4 * (q - 8), x0, x1, x2, x3, tA, tB);
+    }
+  }
+  rA = ((uint64_t)a_hi << 32) | a_lo;
+  rB = ((uint64_t)b_hi << 32) | b_lo;
+}
+
+// Same for any even L: the word's first site has colour-local index
+// i0 = y*L/2 + 64*w, which need not be a multiple of 4, so its 64 sites may
+// straddle 17 Philox blocks starting at i0/4.
+__device__ __forceinline__ void masks_generic(const Geom& g, int64_t y, int32_t w, uint32_t k0,
+                                              uint32_t k1, uint32_t t, uint32_t ctr3, uint32_t tA,
+                                              uint32_t tB, uint64_t& rA, uint64_t& rB) {
+  const int nbits = (w == g.W - 1) ? g.nb_last : 64;
+  const uint64_t i0 = (uint64_t)y * (uint64_t)g.half + 64ull * (uint64_t)w;
+  const int r = (int)(i0 & 3ull);
+  const uint64_t gs = i0 >> 2;
+  const int nc = (r + nbits + 3) >> 2;
+  uint64_t a = 0, b = 0;
+  for (int q = 0; q < nc; ++q) {
+    const uint64_t gq = gs + (uint64_t)q;
+    uint32_t x[4] = {(uint32_t)gq, (uint32_t)(gq >> 32), t, ctr3};
+    philox4x32_10(x[0], x[1], x[2], x[3], k0, k1);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int o = 4 * q + j - r;
+      if (o >= 0 && o < nbits) {
+        a |= (uint64_t)(x[j] < tA) << o;
+        b |= (uint64_t)(x[j] < tB) << o;
+      }
+    }
+  }
+  rA = a;
+  rB = b;
+}
+
+}  // namespace ising

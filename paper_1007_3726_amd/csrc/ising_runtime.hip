@@ -1,0 +1,347 @@
+// Host runtime of the C ABI declared in include/ising.h: handle lifecycle,
+// argument validation, Metropolis thresholds, launch selection, and the
+// conversion between the packed device layout and int8 host spins.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "ising.h"
+#include "ising_kernels.hpp"
+#include "ising_runtime.hpp"
+
+namespace ising {
+
+static thread_local std::string g_last_error;
+
+ising_status fail(ising_status code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+ising_status hip_fail(hipError_t e, const char* what) {
+  return fail(ISING_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+void clear_error() { g_last_error.clear(); }
+
+int64_t words_per_row(int64_t L) { return ((L / 2) + 63) / 64; }
+
+size_t plane_bytes(int64_t L) { return (size_t)L * (size_t)words_per_row(L) * sizeof(uint64_t); }
+
+size_t lattice_bytes(int64_t L) {
+  if (L < 4 || L > kMaxL || (L & 1)) return 0;
+  size_t b = 2 * plane_bytes(L);
+  b = (b + 255) & ~(size_t)255;
+  return b + kScratchBytes;
+}
+
+Geom make_geom(int64_t L) {
+  Geom g;
+  g.L = L;
+  g.W = (int32_t)words_per_row(L);
+  g.half = L / 2;
+  g.nb_last = (int32_t)(g.half - 64 * (int64_t)(g.W - 1));
+  g.L8 = L / 8;
+  return g;
+}
+
+// Section 3: the Boltzmann factor of an uphill move dE, precomputed on the
+// host once per temperature; section 4, Eq. (3): accept iff r < factor.
+// With r = u / 2^32 for a 32-bit uniform u this is u < floor(factor 2^32),
+// clamped to 2^32 - 1 (beta = 0 then accepts with probability 1 - 2^-32).
+uint32_t metropolis_threshold(double beta, int dE) {
+  const double factor = std::exp(-beta * (double)dE);
+  const double scaled = std::floor(std::ldexp(factor, 32));
+  if (scaled >= 4294967295.0) return 0xFFFFFFFFu;
+  if (scaled <= 0.0) return 0u;
+  return (uint32_t)scaled;
+}
+
+int grid_blocks(int64_t work_items, int threads, int max_blocks) {
+  int64_t b = (work_items + threads - 1) / threads;
+  if (b > max_blocks) b = max_blocks;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+
+SweepArgs sweep_args(const ising_lattice* h, uint32_t t, int64_t* EM) {
+  SweepArgs a;
+  a.planes = h->planes;
+  a.plane_words = h->plane_words;
+  a.g = h->g;
+  a.k0 = (uint32_t)h->seed;
+  a.k1 = (uint32_t)(h->seed >> 32);
+  a.sid4 = h->stream_id << 2;
+  a.t = t;
+  a.t4 = h->t4;
+  a.t8 = h->t8;
+  a.EM = EM;
+  return a;
+}
+
+bool use_small_path(const ising_lattice* h) {
+  return 2 * h->plane_words * (int64_t)sizeof(uint64_t) <= h->tune.small_lds_bytes;
+}
+
+ising_status enqueue_sweeps(ising_lattice* h, int64_t n, int64_t* dev_EM) {
+  if (n == 0) return ISING_OK;
+  if (use_small_path(h)) {
+    SmallArgs a;
+    a.planes = h->planes;
+    a.plane_words = h->plane_words;
+    a.g = h->g;
+    a.k0 = (uint32_t)h->seed;
+    a.k1 = (uint32_t)(h->seed >> 32);
+    a.sid4 = h->stream_id << 2;
+    a.t0 = (uint32_t)h->sweep;
+    a.t4 = h->t4;
+    a.t8 = h->t8;
+    a.n = n;
+    a.EM = dev_EM;
+    int threads = (int)std::min<int64_t>(1024, ((h->plane_words + 63) / 64) * 64);
+    hipError_t e = launch_small_sweeps(h->stream, a, threads);
+    if (e != hipSuccess) return hip_fail(e, "small-lattice sweep launch");
+    return ISING_OK;
+  }
+  const int blocks = grid_blocks(h->plane_words, 256, h->tune.max_blocks);
+  for (int64_t k = 0; k < n; ++k) {
+    const uint32_t t = (uint32_t)(h->sweep + (uint64_t)k);
+    SweepArgs a = sweep_args(h, t, dev_EM ? dev_EM + 2 * k : nullptr);
+    hipError_t e = launch_half_sweep(h->stream, 0, a, blocks);
+    if (e != hipSuccess) return hip_fail(e, "colour-0 half-sweep launch");
+    e = launch_half_sweep(h->stream, 1, a, blocks);
+    if (e != hipSuccess) return hip_fail(e, "colour-1 half-sweep launch");
+  }
+  return ISING_OK;
+}
+
+// Host-side unpacking of one packed row pair into int8 spins for the
+// columns [x0, x0 + w) (periodic).
+static void unpack_row(const uint64_t* p0, const uint64_t* p1, int64_t L, int64_t y, int64_t x0,
+                       int64_t w, int8_t* out) {
+  for (int64_t i = 0; i < w; ++i) {
+    const int64_t x = (x0 + i) % L;
+    const int c = (int)((x + y) & 1);
+    const int64_t k = x >> 1;
+    const uint64_t word = (c ? p1 : p0)[k >> 6];
+    out[i] = ((word >> (k & 63)) & 1ull) ? (int8_t)1 : (int8_t)-1;
+  }
+}
+
+}  // namespace ising
+
+using namespace ising;
+
+extern "C" {
+
+const char* ising_last_error(void) { return g_last_error.c_str(); }
+
+const char* ising_version(void) { return "ising-mi355x 0.1 (gfx950)"; }
+
+size_t ising_lattice_bytes(int64_t L) { return lattice_bytes(L); }
+
+ising_status ising_create(int64_t L, uint64_t seed, uint32_t stream_id, int32_t init,
+                          void* dev_buf, size_t dev_bytes, void* hip_stream, ising_t** out) {
+  clear_error();
+  if (!out) return fail(ISING_EINVAL, "ising_create: out is NULL");
+  *out = nullptr;
+  if (L < 4 || (L & 1) || L > kMaxL)
+    return fail(ISING_EINVAL, "ising_create: L=%lld must be even and in [4, %lld]", (long long)L,
+                (long long)kMaxL);
+  if (init < 0 || init > 2) return fail(ISING_EINVAL, "ising_create: init=%d invalid", init);
+  if (stream_id >= (1u << 30))
+    return fail(ISING_EINVAL, "ising_create: stream_id must be < 2^30");
+  if (!dev_buf) return fail(ISING_EINVAL, "ising_create: dev_buf is NULL");
+  if (((uintptr_t)dev_buf) & 255)
+    return fail(ISING_EINVAL, "ising_create: dev_buf must be 256-byte aligned");
+  const size_t need = lattice_bytes(L);
+  if (dev_bytes < need)
+    return fail(ISING_ENOMEM, "ising_create: dev_bytes=%zu < %zu needed for L=%lld", dev_bytes,
+                need, (long long)L);
+  ising_lattice* h = new (std::nothrow) ising_lattice();
+  if (!h) return fail(ISING_ENOMEM, "ising_create: host allocation failed");
+  h->L = L;
+  h->g = make_geom(L);
+  h->plane_words = L * (int64_t)h->g.W;
+  h->planes = (uint64_t*)dev_buf;
+  h->scratch = (int64_t*)((char*)dev_buf + (need - kScratchBytes));
+  h->dev_bytes = dev_bytes;
+  h->seed = seed;
+  h->stream_id = stream_id;
+  h->init = init;
+  h->stream = (hipStream_t)hip_stream;
+  h->sweep = 0;
+  h->beta_set = false;
+  hipError_t e = hipGetDevice(&h->device);
+  if (e != hipSuccess) {
+    delete h;
+    return hip_fail(e, "ising_create: hipGetDevice");
+  }
+  h->tune = default_tuning(L);
+  e = launch_init(h->stream, h->planes, h->g, (uint32_t)seed, (uint32_t)(seed >> 32),
+                  stream_id << 2, init, grid_blocks(2 * h->plane_words, 256, 8192));
+  if (e != hipSuccess) {
+    delete h;
+    return hip_fail(e, "ising_create: init launch");
+  }
+  *out = h;
+  return ISING_OK;
+}
+
+ising_status ising_destroy(ising_t* h) {
+  clear_error();
+  delete h;
+  return ISING_OK;
+}
+
+ising_status ising_set_beta(ising_t* h, double beta) {
+  clear_error();
+  if (!h) return fail(ISING_EINVAL, "ising_set_beta: NULL handle");
+  if (std::isnan(beta) || beta < 0.0)
+    return fail(ISING_EINVAL, "ising_set_beta: beta must be >= 0 or +inf");
+  h->beta = beta;
+  h->t4 = metropolis_threshold(beta, 4);
+  h->t8 = metropolis_threshold(beta, 8);
+  h->beta_set = true;
+  return ISING_OK;
+}
+
+ising_status ising_get_thresholds(const ising_t* h, uint32_t t[2]) {
+  clear_error();
+  if (!h || !t) return fail(ISING_EINVAL, "ising_get_thresholds: NULL argument");
+  if (!h->beta_set) return fail(ISING_EINVAL, "ising_get_thresholds: no beta set");
+  t[0] = h->t4;
+  t[1] = h->t8;
+  return ISING_OK;
+}
+
+ising_status ising_sweep(ising_t* h, int64_t n, int64_t* dev_EM) {
+  clear_error();
+  if (!h) return fail(ISING_EINVAL, "ising_sweep: NULL handle");
+  if (n < 0) return fail(ISING_EINVAL, "ising_sweep: n < 0");
+  if (!h->beta_set) return fail(ISING_EINVAL, "ising_sweep: set beta first");
+  if (h->sweep + (uint64_t)n > (1ull << 32))
+    return fail(ISING_ERANGE, "ising_sweep: sweep counter would pass 2^32 - 1");
+  ising_status st = enqueue_sweeps(h, n, dev_EM);
+  if (st != ISING_OK) return st;
+  h->sweep += (uint64_t)n;
+  return ISING_OK;
+}
+
+ising_status ising_measure(ising_t* h, int64_t* E, int64_t* M) {
+  clear_error();
+  if (!h || !E || !M) return fail(ISING_EINVAL, "ising_measure: NULL argument");
+  hipError_t e = launch_measure(h->stream, h->planes, h->g, h->plane_words, h->scratch,
+                                grid_blocks(h->plane_words, 256, h->tune.max_blocks));
+  if (e != hipSuccess) return hip_fail(e, "ising_measure: launch");
+  int64_t em[2];
+  e = hipMemcpyAsync(em, h->scratch, sizeof(em), hipMemcpyDeviceToHost, h->stream);
+  if (e != hipSuccess) return hip_fail(e, "ising_measure: copy");
+  e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return hip_fail(e, "ising_measure: synchronize");
+  *E = em[0];
+  *M = em[1];
+  return ISING_OK;
+}
+
+ising_status ising_get_window(ising_t* h, int64_t x0, int64_t y0, int64_t w, int64_t hgt,
+                              int8_t* host) {
+  clear_error();
+  if (!h || !host) return fail(ISING_EINVAL, "ising_get_window: NULL argument");
+  const int64_t L = h->L;
+  if (x0 < 0 || y0 < 0 || x0 >= L || y0 >= L || w < 1 || hgt < 1 || w > L || hgt > L)
+    return fail(ISING_EINVAL, "ising_get_window: window out of range");
+  const int64_t W = h->g.W;
+  std::vector<uint64_t> rows(2 * (size_t)hgt * (size_t)W);
+  // rows y0 .. y0+hgt-1 (mod L) of both planes: at most two contiguous chunks each
+  for (int c = 0; c < 2; ++c) {
+    int64_t done = 0;
+    while (done < hgt) {
+      const int64_t y = (y0 + done) % L;
+      const int64_t chunk = std::min<int64_t>(hgt - done, L - y);
+      hipError_t e = hipMemcpyAsync(rows.data() + ((size_t)c * hgt + done) * W,
+                                    h->planes + (size_t)c * h->plane_words + (size_t)y * W,
+                                    (size_t)chunk * W * sizeof(uint64_t), hipMemcpyDeviceToHost,
+                                    h->stream);
+      if (e != hipSuccess) return hip_fail(e, "ising_get_window: copy");
+      done += chunk;
+    }
+  }
+  hipError_t e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return hip_fail(e, "ising_get_window: synchronize");
+  for (int64_t j = 0; j < hgt; ++j) {
+    const int64_t y = (y0 + j) % L;
+    unpack_row(rows.data() + (size_t)j * W, rows.data() + ((size_t)hgt + j) * W, L, y, x0, w,
+               host + j * w);
+  }
+  return ISING_OK;
+}
+
+ising_status ising_get_spins(ising_t* h, int8_t* host) {
+  if (!h) {
+    clear_error();
+    return fail(ISING_EINVAL, "ising_get_spins: NULL handle");
+  }
+  return ising_get_window(h, 0, 0, h->L, h->L, host);
+}
+
+ising_status ising_set_spins(ising_t* h, const int8_t* host) {
+  clear_error();
+  if (!h || !host) return fail(ISING_EINVAL, "ising_set_spins: NULL argument");
+  const int64_t L = h->L, W = h->g.W;
+  std::vector<uint64_t> packed(2 * (size_t)h->plane_words, 0ull);
+  for (int64_t y = 0; y < L; ++y)
+    for (int64_t x = 0; x < L; ++x) {
+      const int8_t v = host[y * L + x];
+      if (v != 1 && v != -1)
+        return fail(ISING_EINVAL, "ising_set_spins: spin at (%lld, %lld) is %d, not +-1",
+                    (long long)x, (long long)y, (int)v);
+      if (v == 1) {
+        const int c = (int)((x + y) & 1);
+        const int64_t k = x >> 1;
+        packed[(size_t)c * h->plane_words + (size_t)y * W + (k >> 6)] |= 1ull << (k & 63);
+      }
+    }
+  hipError_t e = hipMemcpyAsync(h->planes, packed.data(), packed.size() * sizeof(uint64_t),
+                                hipMemcpyHostToDevice, h->stream);
+  if (e != hipSuccess) return hip_fail(e, "ising_set_spins: copy");
+  e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return hip_fail(e, "ising_set_spins: synchronize");
+  return ISING_OK;
+}
+
+ising_status ising_get_sweep(const ising_t* h, uint64_t* t) {
+  clear_error();
+  if (!h || !t) return fail(ISING_EINVAL, "ising_get_sweep: NULL argument");
+  *t = h->sweep;
+  return ISING_OK;
+}
+
+ising_status ising_set_sweep(ising_t* h, uint64_t t) {
+  clear_error();
+  if (!h) return fail(ISING_EINVAL, "ising_set_sweep: NULL handle");
+  if (t >= (1ull << 32)) return fail(ISING_ERANGE, "ising_set_sweep: t must be < 2^32");
+  h->sweep = t;
+  return ISING_OK;
+}
+
+ising_status ising_get_info(const ising_t* h, int64_t* L, int64_t* words_per_row_out,
+                            void** planes) {
+  clear_error();
+  if (!h) return fail(ISING_EINVAL, "ising_get_info: NULL handle");
+  if (L) *L = h->L;
+  if (words_per_row_out) *words_per_row_out = h->g.W;
+  if (planes) *planes = h->planes;
+  return ISING_OK;
+}
+
+}  // extern "C"

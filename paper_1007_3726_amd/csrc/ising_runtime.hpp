@@ -1,0 +1,58 @@
+// Internal host-side declarations of the runtime (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdarg.h>
+#include <stdint.h>
+
+#include "ising.h"
+#include "ising_kernels.hpp"
+
+namespace ising {
+
+constexpr int64_t kMaxL = int64_t(1) << 21;
+constexpr size_t kScratchBytes = 256;
+
+// Launch-shape choices for one lattice size (filled by default_tuning and
+// refined by the autotuner).
+struct Tuning {
+  int64_t small_lds_bytes;  // lattices with both planes <= this run LDS-resident in one workgroup
+  int max_blocks;           // grid cap of the grid-stride half-sweep kernels
+};
+
+Tuning default_tuning(int64_t L);
+
+ising_status fail(ising_status code, const char* fmt, ...);
+ising_status hip_fail(hipError_t e, const char* what);
+void clear_error();
+int64_t words_per_row(int64_t L);
+size_t lattice_bytes(int64_t L);
+Geom make_geom(int64_t L);
+uint32_t metropolis_threshold(double beta, int dE);
+int grid_blocks(int64_t work_items, int threads, int max_blocks);
+
+}  // namespace ising
+
+struct ising_lattice {
+  int64_t L;
+  ising::Geom g;
+  int64_t plane_words;  // L * W
+  uint64_t* planes;     // device: plane 0 then plane 1
+  int64_t* scratch;     // device: 256 B after the planes
+  size_t dev_bytes;
+  uint64_t seed;
+  uint32_t stream_id;
+  int32_t init;
+  double beta;
+  uint32_t t4, t8;
+  bool beta_set;
+  uint64_t sweep;       // counter of the next sweep
+  hipStream_t stream;
+  int device;
+  ising::Tuning tune;
+};
+
+namespace ising {
+ising::SweepArgs sweep_args(const ising_lattice* h, uint32_t t, int64_t* EM);
+ising_status enqueue_sweeps(ising_lattice* h, int64_t n, int64_t* dev_EM);
+}  // namespace ising

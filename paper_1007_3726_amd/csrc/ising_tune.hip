@@ -1,0 +1,14 @@
+// Launch-shape defaults per lattice size.
+#include "ising_runtime.hpp"
+
+namespace ising {
+
+Tuning default_tuning(int64_t L) {
+  (void)L;
+  Tuning t;
+  t.small_lds_bytes = 4096;  // L <= 128 runs in one LDS-resident workgroup
+  t.max_blocks = 2048;
+  return t;
+}
+
+}  // namespace ising

@@ -1,0 +1,231 @@
+"""ctypes binding of the C ABI in include/ising.h (argument marshalling only).
+
+Every computation runs in libising.so (HIP kernels for gfx950).  PyTorch is
+used only to allocate device memory (uint8 tensors) and to name HIP streams.
+If the library is missing this module raises: there is no CPU fallback.
+"""
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libising.so")
+
+ISING_OK = 0
+ISING_AGAIN = 1
+ISING_EINVAL = -1
+ISING_ENOMEM = -2
+ISING_EDEVICE = -3
+ISING_ENOTFOUND = -4
+ISING_ERANGE = -5
+
+INIT_COLD_UP = 0
+INIT_COLD_DOWN = 1
+INIT_HOT = 2
+
+REQ_RECORD_SERIES = 1
+REQ_RETURN_SPINS = 2
+
+
+class IsingError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("ising error %d: %s" % (code, msg))
+        self.code = code
+
+
+class ising_request(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_int64), ("beta", ctypes.c_double), ("seed", ctypes.c_uint64),
+                ("stream_id", ctypes.c_uint32), ("init", ctypes.c_int32),
+                ("n_sweeps", ctypes.c_int64), ("n_discard", ctypes.c_int64),
+                ("flags", ctypes.c_uint32), ("EM_series", ctypes.POINTER(ctypes.c_int64)),
+                ("spins_out", ctypes.POINTER(ctypes.c_int8))]
+
+
+class ising_result(ctypes.Structure):
+    _fields_ = [("ticket", ctypes.c_uint64), ("status", ctypes.c_int32),
+                ("E_final", ctypes.c_int64), ("M_final", ctypes.c_int64),
+                ("sweeps_done", ctypes.c_uint64), ("sum_M2", ctypes.c_double),
+                ("sum_M4", ctypes.c_double), ("n_kept", ctypes.c_int64),
+                ("t_arrive", ctypes.c_double), ("t_admit", ctypes.c_double),
+                ("t_done", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libising.so (built by paper_1007_3726_amd/build.py); raise if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libising.so is not built (run __graft_entry__.build()); "
+                           "there is no fallback path")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, u32, u64 = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32,
+                              ctypes.c_uint64)
+    P = ctypes.POINTER
+    sig = {
+        "ising_last_error": ([], ctypes.c_char_p),
+        "ising_version": ([], ctypes.c_char_p),
+        "ising_lattice_bytes": ([i64], ctypes.c_size_t),
+        "ising_create": ([i64, u64, u32, i32, vp, ctypes.c_size_t, vp, P(vp)], i32),
+        "ising_destroy": ([vp], i32),
+        "ising_set_beta": ([vp, ctypes.c_double], i32),
+        "ising_get_thresholds": ([vp, P(u32)], i32),
+        "ising_sweep": ([vp, i64, vp], i32),
+        "ising_measure": ([vp, P(i64), P(i64)], i32),
+        "ising_get_spins": ([vp, vp], i32),
+        "ising_set_spins": ([vp, vp], i32),
+        "ising_get_window": ([vp, i64, i64, i64, i64, vp], i32),
+        "ising_get_sweep": ([vp, P(u64)], i32),
+        "ising_set_sweep": ([vp, u64], i32),
+        "ising_get_info": ([vp, P(i64), P(i64), P(vp)], i32),
+        "ising_multi_sweep": ([P(vp), i32, i64, P(vp)], i32),
+        "ising_server_create": ([vp, ctypes.c_size_t, vp, i32, P(vp)], i32),
+        "ising_batch_submit": ([vp, P(ising_request), i32, P(u64)], i32),
+        "ising_server_step": ([vp], i32),
+        "ising_poll": ([vp, u64, P(ising_result)], i32),
+        "ising_server_inject_fault": ([vp, i64], i32),
+        "ising_server_stats": ([vp, P(i64)], i32),
+        "ising_server_destroy": ([vp], i32),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = L
+    return _lib
+
+
+def check(code: int, ok=(ISING_OK,)) -> int:
+    if code not in ok:
+        raise IsingError(code, lib().ising_last_error().decode())
+    return code
+
+
+def _stream_ptr(stream) -> int:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream)
+
+
+def _dev_alloc(nbytes: int, device):
+    import torch
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+# ---------------------------------------------------------------------------
+# Module-level functions with the ABI's names
+# ---------------------------------------------------------------------------
+def ising_lattice_bytes(L: int) -> int:
+    return int(lib().ising_lattice_bytes(L))
+
+
+def ising_version() -> str:
+    return lib().ising_version().decode()
+
+
+class Lattice:
+    """One L x L lattice whose packed planes live in a torch uint8 tensor."""
+
+    def __init__(self, L: int, seed: int = 1, stream_id: int = 0, init: int = INIT_HOT,
+                 beta: Optional[float] = None, device="cuda", stream=None):
+        import torch
+        nbytes = ising_lattice_bytes(L)
+        if nbytes == 0:
+            raise IsingError(ISING_EINVAL, "invalid lattice side %r" % (L,))
+        self.L = int(L)
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.buf = _dev_alloc(nbytes, self.device)
+        h = ctypes.c_void_p()
+        check(lib().ising_create(self.L, seed & (2 ** 64 - 1), stream_id, init, self.buf.data_ptr(),
+                                 nbytes, _stream_ptr(self.stream), ctypes.byref(h)))
+        self.h = h
+        if beta is not None:
+            self.set_beta(beta)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().ising_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_beta(self, beta: float):
+        check(lib().ising_set_beta(self.h, float(beta)))
+
+    def thresholds(self):
+        t = (ctypes.c_uint32 * 2)()
+        check(lib().ising_get_thresholds(self.h, t))
+        return int(t[0]), int(t[1])
+
+    def sweep(self, n: int, EM=None):
+        """Enqueue n sweeps; EM: None, or a device int64 tensor (n, 2) to fill."""
+        ptr = None
+        if EM is not None:
+            assert EM.dtype.itemsize == 8 and EM.is_cuda and EM.numel() >= 2 * n
+            assert EM.is_contiguous()
+            ptr = EM.data_ptr()
+        check(lib().ising_sweep(self.h, int(n), ptr))
+
+    def sweep_em(self, n: int):
+        """n sweeps; returns the (n, 2) int64 device tensor of (E, M) per sweep."""
+        import torch
+        EM = torch.empty((n, 2), dtype=torch.int64, device=self.device)
+        self.sweep(n, EM)
+        return EM
+
+    def measure(self):
+        E, M = ctypes.c_int64(), ctypes.c_int64()
+        check(lib().ising_measure(self.h, ctypes.byref(E), ctypes.byref(M)))
+        return int(E.value), int(M.value)
+
+    def get_spins(self) -> np.ndarray:
+        out = np.empty((self.L, self.L), dtype=np.int8)
+        check(lib().ising_get_spins(self.h, out.ctypes.data))
+        return out
+
+    def set_spins(self, s: np.ndarray):
+        s = np.ascontiguousarray(s, dtype=np.int8)
+        assert s.shape == (self.L, self.L)
+        check(lib().ising_set_spins(self.h, s.ctypes.data))
+
+    def get_window(self, x0: int, y0: int, w: int, h: int) -> np.ndarray:
+        out = np.empty((h, w), dtype=np.int8)
+        check(lib().ising_get_window(self.h, x0, y0, w, h, out.ctypes.data))
+        return out
+
+    @property
+    def sweep_count(self) -> int:
+        t = ctypes.c_uint64()
+        check(lib().ising_get_sweep(self.h, ctypes.byref(t)))
+        return int(t.value)
+
+    @sweep_count.setter
+    def sweep_count(self, t: int):
+        check(lib().ising_set_sweep(self.h, int(t)))
+
+    def planes(self):
+        """(L, W, device address) of the packed planes."""
+        L, W, p = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_void_p()
+        check(lib().ising_get_info(self.h, ctypes.byref(L), ctypes.byref(W), ctypes.byref(p)))
+        return int(L.value), int(W.value), int(p.value or 0)
+
+
+def multi_sweep(lattices: Sequence[Lattice], n: int, EMs=None):
+    """n sweeps on every lattice in one fused launch (same device and stream)."""
+    arr = (ctypes.c_void_p * len(lattices))(*[lat.h.value for lat in lattices])
+    em_arr = None
+    if EMs is not None:
+        em_arr = (ctypes.c_void_p * len(lattices))(
+            *[(e.data_ptr() if e is not None else None) for e in EMs])
+    check(lib().ising_multi_sweep(arr, len(lattices), int(n), em_arr))

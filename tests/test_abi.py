@@ -1,0 +1,71 @@
+"""The C ABI library loads on the CPU and exports every declared symbol;
+argument validation that happens before any device work (CPU only)."""
+import ctypes
+import math
+import re
+import subprocess
+import os
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "ising.h")).read()
+    return sorted(set(re.findall(r"ISING_API[^;(]*?\b(ising_\w+)\s*\(", text, flags=re.S)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1007_3726_amd import ising
+    return ising.lib()
+
+
+def test_header_declares_the_entry_points():
+    names = _declared()
+    for required in ["ising_create", "ising_set_beta", "ising_sweep", "ising_measure",
+                     "ising_batch_submit", "ising_poll", "ising_multi_sweep"]:
+        assert required in names
+
+
+def test_every_declared_symbol_is_exported(L):
+    path = os.path.join(ROOT, "paper_1007_3726_amd", "libising.so")
+    out = subprocess.run(["nm", "-D", "--defined-only", path], capture_output=True, text=True,
+                         check=True).stdout
+    exported = set(re.findall(r"\bT (ising_\w+)", out))
+    missing = [n for n in _declared() if n not in exported]
+    assert not missing, missing
+    for n in _declared():
+        assert hasattr(L, n)
+
+
+def test_lattice_bytes(L):
+    from paper_1007_3726_amd import ising
+    assert ising.ising_lattice_bytes(64) == 2 * 64 * 1 * 8 + 256
+    assert ising.ising_lattice_bytes(16384) == 2 * 16384 * 128 * 8 + 256
+    assert ising.ising_lattice_bytes(262144) == 2 * 262144 * 2048 * 8 + 256
+    assert ising.ising_lattice_bytes(130) == 2 * 130 * 2 * 8 + 256 + (256 - (2 * 130 * 2 * 8) % 256) % 256
+    for bad in (-2, 0, 2, 3, 5, 63, 2 ** 21 + 2):
+        assert ising.ising_lattice_bytes(bad) == 0
+
+
+def test_create_validation_before_device_work(L):
+    h = ctypes.c_void_p()
+    buf = ctypes.c_void_p(4096)  # never dereferenced: validation fails first
+    assert L.ising_create(5, 1, 0, 0, buf, 1 << 20, None, ctypes.byref(h)) == -1
+    assert L.ising_create(64, 1, 0, 3, buf, 1 << 20, None, ctypes.byref(h)) == -1
+    assert L.ising_create(64, 1, 1 << 30, 0, buf, 1 << 20, None, ctypes.byref(h)) == -1
+    assert L.ising_create(64, 1, 0, 0, None, 1 << 20, None, ctypes.byref(h)) == -1
+    assert L.ising_create(64, 1, 0, 0, ctypes.c_void_p(4097), 1 << 20, None, ctypes.byref(h)) == -1
+    assert L.ising_create(64, 1, 0, 0, buf, 100, None, ctypes.byref(h)) == -2
+    assert b"dev_bytes" in L.ising_last_error()
+    assert L.ising_create(64, 1, 0, 0, buf, 1 << 20, None, None) == -1
+
+
+def test_null_handles_are_rejected(L):
+    assert L.ising_set_beta(None, 1.0) == -1
+    assert L.ising_sweep(None, 1, None) == -1
+    assert L.ising_destroy(None) == 0
+    E = ctypes.c_int64()
+    assert L.ising_measure(None, ctypes.byref(E), ctypes.byref(E)) == -1
