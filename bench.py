@@ -1,0 +1,147 @@
+"""Benchmark of the checkerboard Metropolis sweep on one MI355X.
+
+One step = one pass of the hot path over the 16384 x 16384 lattice at
+T = 2.269185 (cold start, packed 64 spins per word): 2000 full sweeps with
+exact per-sweep int64 (E, M), the lattice resident in HBM.  The timed region
+covers exactly `--steps` steps between two synchronisations; value is spin
+updates per ns (N * sweeps / time).
+
+Also reported on the same JSON line:
+  roofline      - the half-sweep kernel against the integer VALU issue peak;
+  cpu_baseline  - the CPU oracle timed on a bounded sample of the same
+                  workload on this host's cores (a baseline, not the target).
+
+Usage: python bench.py [--gpus 1] [--steps 3] [--warmup 1]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import workloads  # noqa: E402
+
+# VALU issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane-operations/s.
+VALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
+# Algorithmic lane-operations per spin update (derivation in the design doc):
+# a quarter of a Philox4x32-10 block (10 rounds x (2 wide multiplies + 2
+# three-input XORs) / 4 = 10), two threshold compares and two bit inserts.
+ALU_OPS_PER_UPDATE = 14.0
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=3)
+    p.add_argument("--warmup", type=int, default=1)
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--cpu-sweeps", type=int, default=4,
+                   help="sweeps of the 16384^2 lattice the oracle runs for the CPU baseline")
+    p.add_argument("--sweeps", type=int, default=None,
+                   help="sweeps per step (default: the workload's 2000); for short profiles")
+    p.add_argument("--copy-calibration", action="store_true",
+                   help="also run a plain 1 GiB device copy, the reference for HBM counters")
+    return p.parse_args()
+
+
+def cpu_baseline(w, sweeps):
+    import oracle
+    threads = oracle.get_threads()
+    s = oracle.init(w.L, w.seed, w.stream_id, w.init)
+    t0 = time.perf_counter()
+    oracle.sweeps(s, 1.0 / w.T, w.seed, w.stream_id, 0, sweeps, record=True)
+    dt = time.perf_counter() - t0
+    ups = w.L * w.L * sweeps / (dt * 1e9)
+    return {"value": ups, "unit": "spin updates/ns", "cores": threads, "kind": "oracle",
+            "sample": "%d sweeps of the %dx%d lattice (cold start, T=%r), %.1f s"
+                      % (sweeps, w.L, w.L, w.T, dt)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (each lattice is held whole by one "
+              "MI355X); --gpus %d is not supported" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1007_3726_amd import ising
+
+    w = workloads.LARGE
+    if args.sweeps is not None:
+        import dataclasses
+        w = dataclasses.replace(w, sweeps=args.sweeps)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream(dev)
+    lat = ising.Lattice(w.L, seed=w.seed, stream_id=w.stream_id, init=w.init, beta=1.0 / w.T,
+                        device=dev, stream=stream)
+    EM = torch.empty((w.sweeps, 2), dtype=torch.int64, device=dev)
+    print("bench: %s L=%d T=%r sweeps/step=%d warmup=%d steps=%d"
+          % (w.name, w.L, w.T, w.sweeps, args.warmup, args.steps), file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        lat.sweep(w.sweeps, EM)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    t_wall = time.perf_counter()
+    start.record(stream)
+    for _ in range(args.steps):
+        lat.sweep(w.sweeps, EM)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_wall
+    ms = start.elapsed_time(stop)
+    N = w.L * w.L
+    updates = N * w.sweeps * args.steps
+    value = updates / (ms * 1e6)
+    # consistency check of the last step's final (E, M) against a recount
+    last = EM[-1].cpu().tolist()
+    assert tuple(last) == lat.measure(), "fused E/M disagrees with a recount"
+
+    launches = 2 * w.sweeps * args.steps
+    launch_us = ms * 1e3 / launches
+    ops_per_launch = ALU_OPS_PER_UPDATE * N / 2
+    achieved = ops_per_launch / (launch_us * 1e-6)
+    result = {
+        "metric": "spin updates/ns (packed checkerboard), batched vs plain; p50/p99 solve latency",
+        "value": round(value, 2),
+        "unit": "spin updates/ns",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": "plain %dx%d periodic lattice, T=%r, cold start, %d sweeps/step, "
+                               "per-sweep int64 E/M" % (w.L, w.L, w.T, w.sweeps),
+                   "L": w.L, "T": w.T, "sweeps_per_step": w.sweeps, "form": "plain"},
+        "roofline": {"bound": "alu", "achieved": round(achieved / 1e12, 3),
+                     "peak": round(VALU_PEAK_LANE_OPS / 1e12, 3), "unit": "Tops/s",
+                     "frac": round(achieved / VALU_PEAK_LANE_OPS, 4), "traffic": None,
+                     "kernel": "k_tile_sweep", "avg_launch_us": round(launch_us, 3),
+                     "ops_per_update": ALU_OPS_PER_UPDATE},
+        "wall_s": round(wall, 3),
+    }
+    if args.copy_calibration:
+        # a plain copy of known size: 1 GiB read + 1 GiB written
+        src = torch.ones(1 << 30, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        result["copy_calibration_bytes"] = 1 << 30
+        del src, dst
+    if not args.no_cpu_baseline:
+        print("bench: CPU oracle baseline (%d sweeps)" % args.cpu_sweeps, file=sys.stderr,
+              flush=True)
+        result["cpu_baseline"] = cpu_baseline(w, args.cpu_sweeps)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

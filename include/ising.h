@@ -40,7 +40,7 @@
  *   plane 0 (colour 0) then plane 1 (colour 1), each L rows of W uint64
  *   words, W = ceil((L/2)/64).  Bit b of word w in row y of plane c holds
  *   the site x = 2*(64*w + b) + ((y + c) & 1); padding bits are zero.
- *   A 256-byte scratch area follows the planes.
+ *   A scratch area of 256 + 65536 bytes follows the planes (E/M partials).
  */
 #ifndef ISING_H
 #define ISING_H
@@ -80,7 +80,7 @@ ISING_API const char *ising_last_error(void);
 /* Library version string. */
 ISING_API const char *ising_version(void);
 
-/* Device bytes a lattice of side L needs (planes + 256 B scratch); 0 if L
+/* Device bytes a lattice of side L needs (planes + scratch); 0 if L
  * is invalid (odd, < 4 or > 2^21). */
 ISING_API size_t ising_lattice_bytes(int64_t L);
 

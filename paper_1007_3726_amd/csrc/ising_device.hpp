@@ -165,4 +165,60 @@ __device__ __forceinline__ void masks_generic(const Geom& g, int64_t y, int32_t 
   rB = b;
 }
 
+// Compare the four outputs of one Philox block with t4 and t8 and shift the
+// results into the 32-bit accumulators: acc = 2*acc + [x < t] for x3, x2,
+// x1, x0 in that order, so that x0 lands in the lowest of the four new bit
+// positions.  Each compare writes a lane mask into its own SGPR pair and
+// each v_addc_co_u32 consumes one as carry-in; every mask is read at least
+// three instructions after it is written (gfx950 needs two wait states
+// between a VALU SGPR write and its use as a carry).
+__device__ __forceinline__ void shift_in4(uint32_t& a4, uint32_t& a8, uint32_t x0, uint32_t x1,
+                                          uint32_t x2, uint32_t x3, uint32_t t4, uint32_t t8) {
+  uint64_t c0, c1, c2, c3, d;
+  asm("v_cmp_gt_u32_e64 %[c0], %[t4], %[x3]\n\t"
+      "v_cmp_gt_u32_e64 %[c1], %[t8], %[x3]\n\t"
+      "v_cmp_gt_u32_e64 %[c2], %[t4], %[x2]\n\t"
+      "v_cmp_gt_u32_e64 %[c3], %[t8], %[x2]\n\t"
+      "v_addc_co_u32_e64 %[a4], %[d], %[a4], %[a4], %[c0]\n\t"
+      "v_addc_co_u32_e64 %[a8], %[d], %[a8], %[a8], %[c1]\n\t"
+      "v_cmp_gt_u32_e64 %[c0], %[t4], %[x1]\n\t"
+      "v_cmp_gt_u32_e64 %[c1], %[t8], %[x1]\n\t"
+      "v_addc_co_u32_e64 %[a4], %[d], %[a4], %[a4], %[c2]\n\t"
+      "v_addc_co_u32_e64 %[a8], %[d], %[a8], %[a8], %[c3]\n\t"
+      "v_cmp_gt_u32_e64 %[c2], %[t4], %[x0]\n\t"
+      "v_cmp_gt_u32_e64 %[c3], %[t8], %[x0]\n\t"
+      "v_addc_co_u32_e64 %[a4], %[d], %[a4], %[a4], %[c0]\n\t"
+      "v_addc_co_u32_e64 %[a8], %[d], %[a8], %[a8], %[c1]\n\t"
+      "v_addc_co_u32_e64 %[a4], %[d], %[a4], %[a4], %[c2]\n\t"
+      "v_addc_co_u32_e64 %[a8], %[d], %[a8], %[a8], %[c3]"
+      : [a4] "+v"(a4), [a8] "+v"(a8), [c0] "=&s"(c0), [c1] "=&s"(c1), [c2] "=&s"(c2),
+        [c3] "=&s"(c3), [d] "=&s"(d)
+      : [x0] "v"(x0), [x1] "v"(x1), [x2] "v"(x2), [x3] "v"(x3), [t4] "s"(t4), [t8] "s"(t8));
+}
+
+// Masks for one word whose Philox blocks are lo + q, q < nq, all with the
+// same high counter word `hi` (no carry out of lo + q): block q covers bits
+// 4q..4q+3.  Blocks are visited from q = 15 down to 0 so that the shift-in
+// order leaves block 0 in the lowest bits; with FULL every word has 16
+// blocks, otherwise blocks q >= nq are skipped and their bits stay zero.
+template <bool FULL>
+__device__ __forceinline__ void masks_shift(uint32_t lo, uint32_t hi, int nq, uint32_t k0,
+                                            uint32_t k1, uint32_t t, uint32_t ctr3, uint32_t t4,
+                                            uint32_t t8, uint64_t& r4, uint64_t& r8) {
+  uint32_t a4_hi = 0, a8_hi = 0, a4_lo = 0, a8_lo = 0;
+#pragma unroll
+  for (int q = 15; q >= 0; --q) {
+    if (FULL || q < nq) {
+      uint32_t x0 = lo + (uint32_t)q, x1 = hi, x2 = t, x3 = ctr3;
+      philox4x32_10(x0, x1, x2, x3, k0, k1);
+      if (q >= 8)
+        shift_in4(a4_hi, a8_hi, x0, x1, x2, x3, t4, t8);
+      else
+        shift_in4(a4_lo, a8_lo, x0, x1, x2, x3, t4, t8);
+    }
+  }
+  r4 = ((uint64_t)a4_hi << 32) | a4_lo;
+  r8 = ((uint64_t)a8_hi << 32) | a8_lo;
+}
+
 }  // namespace ising

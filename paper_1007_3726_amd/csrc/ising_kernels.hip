@@ -213,8 +213,214 @@ __global__ __launch_bounds__(1024) void k_small_sweeps(SmallArgs a) {
 }
 
 // ---------------------------------------------------------------------
+// Tiled half-sweep for L % 8 == 0.
+//
+// Work unit: a tile of TR = 4*R*RPW rows x TW words of colour C.  A wave
+// processes RPW row groups of the tile one after the other, one word per
+// lane per group (W >= 64: a row group is one row of a 64-word segment;
+// W < 64: a row group is R = floor(64/W) whole rows).  The other colour's
+// rows y0-1 .. y0+TR and words w0-1 .. w0+TW (periodic) are staged in LDS
+// with coalesced loads, so each neighbour word is read from HBM/L2 about
+// once per tile instead of three times.  The Philox block index of word
+// (y, w) is y*L/8 + 16*w + q; its high word is 0 (hi_mode 0) or uniform
+// over the wave's row (hi_mode 1), so only the low word varies per lane.
+//
+// Workgroups walk the tiles with a grid stride; logical block numbers are
+// grouped by XCD (hardware dispatches block b to XCD b mod 8), so that
+// vertically adjacent tiles share one L2.
+//
+// E/M (colour 1): each block writes its (anti-aligned bond, up spin) counts
+// to part[block]; block 0 of the next colour-0 pass (or launch_finalize_em)
+// reduces them into (E, M) = (2A - 2N, 2P - N).
+// ---------------------------------------------------------------------
+__device__ __forceinline__ void finalize_partials(const uint64_t* part, int nblocks, int64_t L,
+                                                  int64_t* EM, uint64_t* red64) {
+  uint64_t a = 0, p = 0;
+  for (int i = threadIdx.x; i < nblocks; i += blockDim.x) {
+    a += part[2 * i];
+    p += part[2 * i + 1];
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    a += __shfl_xor(a, off, 64);
+    p += __shfl_xor(p, off, 64);
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) {
+    red64[2 * wave] = a;
+    red64[2 * wave + 1] = p;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint64_t sa = 0, sp = 0;
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) {
+      sa += red64[2 * i];
+      sp += red64[2 * i + 1];
+    }
+    EM[0] = 2 * (int64_t)sa - 2 * L * L;
+    EM[1] = 2 * (int64_t)sp - L * L;
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ int64_t wrap_row(int64_t y, int64_t L) {
+  return y < 0 ? y + L : (y >= L ? y - L : y);
+}
+
+template <int C, bool EM, bool FULL, bool WIDE>
+__global__ __launch_bounds__(256) void k_tile_sweep(TileArgs a) {
+  __shared__ uint64_t tile[kTileLdsMaxWords];
+  __shared__ uint64_t red64[8];
+  __shared__ uint32_t red[8];
+  const Geom g = a.g;
+  uint64_t* __restrict__ self = a.planes + (C ? a.plane_words : 0);
+  const uint64_t* __restrict__ other = a.planes + (C ? 0 : a.plane_words);
+
+  if (C == 0 && a.prev_EM != nullptr && blockIdx.x == 0)
+    finalize_partials(a.prev_part, a.prev_blocks, g.L, a.prev_EM, red64);
+
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int TW = a.TW, R = a.R, RPW = a.RPW;
+  const int TR = 4 * R * RPW;  // rows per tile
+  const int SW = TW + 2;       // staged row width
+  const int SR = TR + 2;       // staged rows
+  // position of this lane inside a row group
+  int r_off, w_l;
+  bool lane_ok;
+  if (WIDE) {
+    r_off = 0;
+    w_l = lane;
+    lane_ok = true;
+  } else {
+    r_off = lane / TW;
+    w_l = lane - r_off * TW;
+    lane_ok = r_off < R;
+  }
+  // staging map: a wave pass loads P staged rows (WIDE: one row of 66 words,
+  // lanes 0 and 1 also load words 64 and 65)
+  int st_r, st_c, P;
+  if (WIDE) {
+    P = 1;
+    st_r = 0;
+    st_c = lane;
+  } else {
+    P = 64 / SW;
+    st_r = lane / SW;
+    st_c = lane - st_r * SW;
+    if (st_r >= P) st_r = -1;
+  }
+  // logical block number grouped by XCD
+  const int G = gridDim.x;
+  const int b = blockIdx.x;
+  const int lb = (G % 8 == 0) ? (b % 8) * (G / 8) + b / 8 : b;
+
+  uint32_t anti = 0, up = 0;
+  for (int64_t tidx = lb; tidx < a.tiles; tidx += G) {
+    const int64_t y0 = (tidx / a.segs) * TR;
+    const int32_t w0 = WIDE ? (int32_t)(tidx % a.segs) * 64 : 0;
+    for (int rr0 = wave * P; rr0 < SR; rr0 += 4 * P) {
+      const int rr = rr0 + st_r;
+      if (st_r >= 0 && rr < SR) {
+        const int64_t yy = wrap_row(y0 - 1 + rr, g.L);
+        const int32_t ww = (int32_t)wrap_row(w0 - 1 + st_c, g.W);
+        tile[rr * SW + st_c] = other[yy * g.W + ww];
+        if (WIDE && lane < 2) {
+          const int32_t w2 = (int32_t)wrap_row(w0 + 63 + lane, g.W);
+          tile[rr * SW + 64 + lane] = other[yy * g.W + w2];
+        }
+      }
+    }
+    __syncthreads();
+    for (int j = 0; j < RPW; ++j) {
+      const int r_l = (wave * RPW + j) * R + r_off;
+      const int64_t y = y0 + r_l;
+      const int32_t w = w0 + w_l;
+      if (!(lane_ok && y < g.L && w < g.W)) continue;
+      const uint64_t s = self[y * g.W + w];
+      const int base = (r_l + 1) * SW + (w_l + 1);
+      Nbr n;
+      n.n0 = tile[base];
+      n.n2 = tile[base - SW];
+      n.n3 = tile[base + SW];
+      if (((y + C) & 1) == 0) {
+        const uint64_t left = tile[base - 1];
+        n.n1 = (n.n0 << 1) | ((w > 0) ? (left >> 63) : ((left >> (g.nb_last - 1)) & 1ull));
+      } else {
+        const uint64_t right = tile[base + 1];
+        n.n1 = (w < g.W - 1) ? ((n.n0 >> 1) | (right << 63))
+                             : ((n.n0 >> 1) | ((right & 1ull) << (g.nb_last - 1)));
+      }
+      uint32_t lo, hi;
+      if (a.hi_mode == 0) {
+        lo = (uint32_t)y * (uint32_t)g.L8 + 16u * (uint32_t)w;
+        hi = 0;
+      } else {
+        const uint64_t gy =
+            (uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)y) * (uint64_t)g.L8;
+        hi = (uint32_t)(gy >> 32);
+        lo = (uint32_t)gy + 16u * (uint32_t)w;
+      }
+      const int nq = (FULL || w < g.W - 1) ? 16 : (g.nb_last >> 2);
+      uint64_t r4, r8;
+      masks_shift<FULL>(lo, hi, nq, a.k0, a.k1, a.t, a.sid4 | C, a.t4, a.t8, r4, r8);
+      const uint64_t valid = (FULL || w < g.W - 1) ? ~0ull : low_mask(g.nb_last);
+      const uint64_t s_new = s ^ (flip_mask(s, n, r4, r8) & valid);
+      self[y * g.W + w] = s_new;
+      if (C == 1 && EM) count_word(s_new, n, valid, anti, up);
+    }
+    __syncthreads();
+  }
+  if (C == 1 && EM) {
+    block_sum2(anti, up, red);
+    if (threadIdx.x == 0) {
+      a.part[2 * blockIdx.x] = anti;
+      a.part[2 * blockIdx.x + 1] = up;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_finalize_em(const uint64_t* part, int nblocks, int64_t L,
+                                                     int64_t* EM) {
+  __shared__ uint64_t red64[8];
+  finalize_partials(part, nblocks, L, EM, red64);
+}
+
+// ---------------------------------------------------------------------
 // Host-side launchers
 // ---------------------------------------------------------------------
+hipError_t launch_tile_sweep(hipStream_t st, int colour, const TileArgs& a, int blocks) {
+  const bool em = (colour == 1) ? (a.part != nullptr) : false;
+  const bool full = a.g.nb_last == 64;
+  const bool wide = a.g.W >= 64;
+#define ISING_TILE(C, E, F, WI) \
+  hipLaunchKernelGGL((k_tile_sweep<C, E, F, WI>), dim3(blocks), dim3(256), 0, st, a)
+#define ISING_TILE_FW(C, E)                                   \
+  do {                                                        \
+    if (full) {                                               \
+      if (wide) ISING_TILE(C, E, true, true);                 \
+      else ISING_TILE(C, E, true, false);                     \
+    } else {                                                  \
+      if (wide) ISING_TILE(C, E, false, true);                \
+      else ISING_TILE(C, E, false, false);                    \
+    }                                                         \
+  } while (0)
+  if (colour == 0)
+    ISING_TILE_FW(0, false);
+  else if (em)
+    ISING_TILE_FW(1, true);
+  else
+    ISING_TILE_FW(1, false);
+#undef ISING_TILE_FW
+#undef ISING_TILE
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize_em(hipStream_t st, const uint64_t* part, int blocks, int64_t L,
+                              int64_t* EM) {
+  hipLaunchKernelGGL(k_finalize_em, dim3(1), dim3(256), 0, st, part, blocks, L, EM);
+  return hipGetLastError();
+}
 hipError_t launch_init(hipStream_t st, uint64_t* planes, const Geom& g, uint32_t k0, uint32_t k1,
                        uint32_t sid4, int init, int blocks) {
   const bool aligned = (g.L % 8) == 0;

@@ -28,6 +28,33 @@ struct SmallArgs {
   int64_t* EM;          // n x 2, or null
 };
 
+// Tiled half-sweep (L % 8 == 0): a workgroup of four waves handles a tile
+// of 4*R rows x TW words of one colour; the neighbour rows of the other
+// colour are staged in LDS once per tile.
+constexpr int kTileLdsMaxWords = 2048;
+constexpr int kMaxSweepBlocks = 2048;
+
+struct TileArgs {
+  uint64_t* planes;
+  int64_t plane_words;
+  Geom g;
+  uint32_t k0, k1, sid4, t, t4, t8;
+  int32_t TW;       // tile width in words: 64 when W >= 64, else W
+  int32_t R;        // rows per row group: 1 when W >= 64, else floor(64 / W)
+  int32_t RPW;      // row groups per wave in one tile
+  int32_t segs;     // 64-word segments per row (1 when W < 64)
+  int64_t tiles;    // ceil(L / (4 R RPW)) * segs
+  int32_t hi_mode;  // 0: every Philox block index < 2^32; 1: high word uniform per row
+  uint64_t* part;   // colour 1 with E/M: per-block (anti-aligned bonds, up spins)
+  int64_t* prev_EM;           // colour 0: (E, M) slot of the previous sweep to finalise
+  const uint64_t* prev_part;  // partials of the previous sweep
+  int32_t prev_blocks;
+};
+
+hipError_t launch_tile_sweep(hipStream_t st, int colour, const TileArgs& a, int blocks);
+hipError_t launch_finalize_em(hipStream_t st, const uint64_t* part, int blocks, int64_t L,
+                              int64_t* EM);
+
 hipError_t launch_init(hipStream_t st, uint64_t* planes, const Geom& g, uint32_t k0, uint32_t k1,
                        uint32_t sid4, int init, int blocks);
 hipError_t launch_half_sweep(hipStream_t st, int colour, const SweepArgs& a, int blocks);

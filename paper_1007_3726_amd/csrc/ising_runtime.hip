@@ -88,6 +88,49 @@ SweepArgs sweep_args(const ising_lattice* h, uint32_t t, int64_t* EM) {
   return a;
 }
 
+// Shape of the tiled half-sweep for this lattice; false when it does not
+// apply (L % 8 != 0, or Philox block indices that cross 2^32 inside a row).
+bool tile_args(const ising_lattice* h, TileArgs* out) {
+  const int64_t L = h->L, W = h->g.W;
+  if (L % 8 != 0) return false;
+  TileArgs a;
+  std::memset(&a, 0, sizeof(a));
+  const bool wide = W >= 64;
+  a.TW = wide ? 64 : (int32_t)W;
+  a.R = wide ? 1 : (int32_t)(64 / W);
+  a.segs = wide ? (int32_t)((W + 63) / 64) : 1;
+  // row groups per wave: as many as keep >= 2048 tiles (8 per CU) and fit in LDS
+  a.RPW = 1;
+  for (int rpw = 4; rpw > 1; rpw >>= 1) {
+    const int64_t TR = 4 * (int64_t)a.R * rpw;
+    const int64_t tiles = ((L + TR - 1) / TR) * a.segs;
+    if (tiles >= 2048 && (TR + 2) * (a.TW + 2) <= kTileLdsMaxWords) {
+      a.RPW = rpw;
+      break;
+    }
+  }
+  const int64_t TR = 4 * (int64_t)a.R * a.RPW;
+  a.tiles = ((L + TR - 1) / TR) * a.segs;
+  if ((TR + 2) * (a.TW + 2) > kTileLdsMaxWords) return false;
+  const bool pow2 = (L & (L - 1)) == 0;
+  if ((uint64_t)L * (uint64_t)L / 8 <= (1ull << 32))
+    a.hi_mode = 0;
+  else if (wide && pow2)
+    a.hi_mode = 1;
+  else
+    return false;
+  a.planes = h->planes;
+  a.plane_words = h->plane_words;
+  a.g = h->g;
+  a.k0 = (uint32_t)h->seed;
+  a.k1 = (uint32_t)(h->seed >> 32);
+  a.sid4 = h->stream_id << 2;
+  a.t4 = h->t4;
+  a.t8 = h->t8;
+  *out = a;
+  return true;
+}
+
 bool use_small_path(const ising_lattice* h) {
   return 2 * h->plane_words * (int64_t)sizeof(uint64_t) <= h->tune.small_lds_bytes;
 }
@@ -110,6 +153,30 @@ ising_status enqueue_sweeps(ising_lattice* h, int64_t n, int64_t* dev_EM) {
     int threads = (int)std::min<int64_t>(1024, ((h->plane_words + 63) / 64) * 64);
     hipError_t e = launch_small_sweeps(h->stream, a, threads);
     if (e != hipSuccess) return hip_fail(e, "small-lattice sweep launch");
+    return ISING_OK;
+  }
+  TileArgs ta;
+  if (tile_args(h, &ta)) {
+    const int blocks = (int)std::min<int64_t>(ta.tiles, std::min(h->tune.max_blocks,
+                                                                 kMaxSweepBlocks));
+    for (int64_t k = 0; k < n; ++k) {
+      ta.t = (uint32_t)(h->sweep + (uint64_t)k);
+      ta.prev_EM = (dev_EM && k > 0) ? dev_EM + 2 * (k - 1) : nullptr;
+      ta.prev_part = h->part[(k + 1) & 1];
+      ta.prev_blocks = blocks;
+      ta.part = nullptr;
+      hipError_t e = launch_tile_sweep(h->stream, 0, ta, blocks);
+      if (e != hipSuccess) return hip_fail(e, "colour-0 tiled half-sweep launch");
+      ta.prev_EM = nullptr;
+      ta.part = dev_EM ? h->part[k & 1] : nullptr;
+      e = launch_tile_sweep(h->stream, 1, ta, blocks);
+      if (e != hipSuccess) return hip_fail(e, "colour-1 tiled half-sweep launch");
+    }
+    if (dev_EM) {
+      hipError_t e = launch_finalize_em(h->stream, h->part[(n - 1) & 1], blocks, h->L,
+                                        dev_EM + 2 * (n - 1));
+      if (e != hipSuccess) return hip_fail(e, "E/M finalisation launch");
+    }
     return ISING_OK;
   }
   const int blocks = grid_blocks(h->plane_words, 256, h->tune.max_blocks);
@@ -174,6 +241,8 @@ ising_status ising_create(int64_t L, uint64_t seed, uint32_t stream_id, int32_t 
   h->plane_words = L * (int64_t)h->g.W;
   h->planes = (uint64_t*)dev_buf;
   h->scratch = (int64_t*)((char*)dev_buf + (need - kScratchBytes));
+  h->part[0] = (uint64_t*)((char*)h->scratch + 256);
+  h->part[1] = h->part[0] + 2 * kMaxSweepBlocks;
   h->dev_bytes = dev_bytes;
   h->seed = seed;
   h->stream_id = stream_id;

@@ -11,7 +11,9 @@
 namespace ising {
 
 constexpr int64_t kMaxL = int64_t(1) << 21;
-constexpr size_t kScratchBytes = 256;
+// scratch after the planes: [0, 256) measurement, then two slots of
+// per-block E/M partials (2 x kMaxSweepBlocks x 16 bytes)
+constexpr size_t kScratchBytes = 256 + 2 * (size_t)kMaxSweepBlocks * 16;
 
 // Launch-shape choices for one lattice size (filled by default_tuning and
 // refined by the autotuner).
@@ -38,7 +40,8 @@ struct ising_lattice {
   ising::Geom g;
   int64_t plane_words;  // L * W
   uint64_t* planes;     // device: plane 0 then plane 1
-  int64_t* scratch;     // device: 256 B after the planes
+  int64_t* scratch;     // device: scratch area after the planes
+  uint64_t* part[2];    // device: E/M partial slots inside the scratch area
   size_t dev_bytes;
   uint64_t seed;
   uint32_t stream_id;

@@ -42,10 +42,16 @@ def test_every_declared_symbol_is_exported(L):
 
 def test_lattice_bytes(L):
     from paper_1007_3726_amd import ising
-    assert ising.ising_lattice_bytes(64) == 2 * 64 * 1 * 8 + 256
-    assert ising.ising_lattice_bytes(16384) == 2 * 16384 * 128 * 8 + 256
-    assert ising.ising_lattice_bytes(262144) == 2 * 262144 * 2048 * 8 + 256
-    assert ising.ising_lattice_bytes(130) == 2 * 130 * 2 * 8 + 256 + (256 - (2 * 130 * 2 * 8) % 256) % 256
+    scratch = 256 + 2 * 2048 * 16
+
+    def planes(L):
+        b = 2 * L * (((L // 2) + 63) // 64) * 8
+        return (b + 255) // 256 * 256
+
+    assert ising.ising_lattice_bytes(64) == planes(64) + scratch
+    assert ising.ising_lattice_bytes(16384) == 2 * 16384 * 128 * 8 + scratch
+    assert ising.ising_lattice_bytes(262144) == 2 * 262144 * 2048 * 8 + scratch
+    assert ising.ising_lattice_bytes(130) == planes(130) + scratch
     for bad in (-2, 0, 2, 3, 5, 63, 2 ** 21 + 2):
         assert ising.ising_lattice_bytes(bad) == 0
 
