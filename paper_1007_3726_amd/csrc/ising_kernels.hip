@@ -267,18 +267,16 @@ __device__ __forceinline__ int64_t wrap_row(int64_t y, int64_t L) {
   return y < 0 ? y + L : (y >= L ? y - L : y);
 }
 
-template <int C, bool EM, bool FULL, bool WIDE>
-__global__ __launch_bounds__(256) void k_tile_sweep(TileArgs a) {
-  __shared__ uint64_t tile[kTileLdsMaxWords];
-  __shared__ uint64_t red64[8];
-  __shared__ uint32_t red[8];
-  const Geom g = a.g;
-  uint64_t* __restrict__ self = a.planes + (C ? a.plane_words : 0);
-  const uint64_t* __restrict__ other = a.planes + (C ? 0 : a.plane_words);
-
-  if (C == 0 && a.prev_EM != nullptr && blockIdx.x == 0)
-    finalize_partials(a.prev_part, a.prev_blocks, g.L, a.prev_EM, red64);
-
+// One colour step of one lattice over the tiles first, first + stride, ...
+// of the tiled layout described above.  `colour` and `em` are uniform; the
+// callers pass constants where they can.  Ends with a block barrier.
+template <bool FULL, bool WIDE>
+__device__ __forceinline__ void sweep_tiles(const TileArgs& a, int colour, bool em,
+                                            int64_t first, int64_t stride, uint64_t* tile,
+                                            uint32_t& anti, uint32_t& up) {
+  const Geom& g = a.g;
+  uint64_t* __restrict__ self = a.planes + (colour ? a.plane_words : 0);
+  const uint64_t* __restrict__ other = a.planes + (colour ? 0 : a.plane_words);
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int TW = a.TW, R = a.R, RPW = a.RPW;
@@ -310,13 +308,8 @@ __global__ __launch_bounds__(256) void k_tile_sweep(TileArgs a) {
     st_c = lane - st_r * SW;
     if (st_r >= P) st_r = -1;
   }
-  // logical block number grouped by XCD
-  const int G = gridDim.x;
-  const int b = blockIdx.x;
-  const int lb = (G % 8 == 0) ? (b % 8) * (G / 8) + b / 8 : b;
-
-  uint32_t anti = 0, up = 0;
-  for (int64_t tidx = lb; tidx < a.tiles; tidx += G) {
+  const uint32_t ctr3 = a.sid4 | (uint32_t)colour;
+  for (int64_t tidx = first; tidx < a.tiles; tidx += stride) {
     const int64_t y0 = (tidx / a.segs) * TR;
     const int32_t w0 = WIDE ? (int32_t)(tidx % a.segs) * 64 : 0;
     for (int rr0 = wave * P; rr0 < SR; rr0 += 4 * P) {
@@ -343,7 +336,7 @@ __global__ __launch_bounds__(256) void k_tile_sweep(TileArgs a) {
       n.n0 = tile[base];
       n.n2 = tile[base - SW];
       n.n3 = tile[base + SW];
-      if (((y + C) & 1) == 0) {
+      if (((y + colour) & 1) == 0) {
         const uint64_t left = tile[base - 1];
         n.n1 = (n.n0 << 1) | ((w > 0) ? (left >> 63) : ((left >> (g.nb_last - 1)) & 1ull));
       } else {
@@ -363,14 +356,29 @@ __global__ __launch_bounds__(256) void k_tile_sweep(TileArgs a) {
       }
       const int nq = (FULL || w < g.W - 1) ? 16 : (g.nb_last >> 2);
       uint64_t r4, r8;
-      masks_shift<FULL>(lo, hi, nq, a.k0, a.k1, a.t, a.sid4 | C, a.t4, a.t8, r4, r8);
+      masks_shift<FULL>(lo, hi, nq, a.k0, a.k1, a.t, ctr3, a.t4, a.t8, r4, r8);
       const uint64_t valid = (FULL || w < g.W - 1) ? ~0ull : low_mask(g.nb_last);
       const uint64_t s_new = s ^ (flip_mask(s, n, r4, r8) & valid);
       self[y * g.W + w] = s_new;
-      if (C == 1 && EM) count_word(s_new, n, valid, anti, up);
+      if (colour == 1 && em) count_word(s_new, n, valid, anti, up);
     }
     __syncthreads();
   }
+}
+
+template <int C, bool EM, bool FULL, bool WIDE>
+__global__ __launch_bounds__(256) void k_tile_sweep(TileArgs a) {
+  __shared__ uint64_t tile[kTileLdsMaxWords];
+  __shared__ uint64_t red64[8];
+  __shared__ uint32_t red[8];
+  if (C == 0 && a.prev_EM != nullptr && blockIdx.x == 0)
+    finalize_partials(a.prev_part, a.prev_blocks, a.g.L, a.prev_EM, red64);
+  // logical block number grouped by XCD
+  const int G = gridDim.x;
+  const int b = blockIdx.x;
+  const int lb = (G % 8 == 0) ? (b % 8) * (G / 8) + b / 8 : b;
+  uint32_t anti = 0, up = 0;
+  sweep_tiles<FULL, WIDE>(a, C, EM, lb, G, tile, anti, up);
   if (C == 1 && EM) {
     block_sum2(anti, up, red);
     if (threadIdx.x == 0) {
