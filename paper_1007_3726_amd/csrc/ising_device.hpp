@@ -24,7 +24,10 @@ __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
 
 // One Philox4x32-10 block.  Each round is two 32x32->64 multiplies
 // (v_mad_u64_u32, full rate on gfx950) and two three-input XORs; the key
-// schedule is wave-uniform and lives in SGPRs.
+// schedule is wave-uniform.  With BUMP_SALU the round keys are bumped by a
+// scalar add in every round instead of being precomputed, which keeps 18
+// SGPRs free (the scalar adds issue beside the vector work).
+template <bool BUMP_SALU = false>
 __device__ __forceinline__ void philox4x32_10(uint32_t& x0, uint32_t& x1, uint32_t& x2,
                                               uint32_t& x3, uint32_t k0, uint32_t k1) {
 #pragma unroll
@@ -37,8 +40,15 @@ __device__ __forceinline__ void philox4x32_10(uint32_t& x0, uint32_t& x1, uint32
     x3 = (uint32_t)p0;
     x0 = y0;
     x2 = y2;
-    k0 += kW0;
-    k1 += kW1;
+    if (BUMP_SALU) {
+      if (r < 9) {
+        asm("s_add_u32 %0, %0, %1" : "+s"(k0) : "i"(kW0) : "scc");
+        asm("s_add_u32 %0, %0, %1" : "+s"(k1) : "i"(kW1) : "scc");
+      }
+    } else {
+      k0 += kW0;
+      k1 += kW1;
+    }
   }
 }
 
@@ -201,7 +211,7 @@ __device__ __forceinline__ void shift_in4(uint32_t& a4, uint32_t& a8, uint32_t x
 // 4q..4q+3.  Blocks are visited from q = 15 down to 0 so that the shift-in
 // order leaves block 0 in the lowest bits; with FULL every word has 16
 // blocks, otherwise blocks q >= nq are skipped and their bits stay zero.
-template <bool FULL>
+template <bool FULL, bool BUMP_SALU = false>
 __device__ __forceinline__ void masks_shift(uint32_t lo, uint32_t hi, int nq, uint32_t k0,
                                             uint32_t k1, uint32_t t, uint32_t ctr3, uint32_t t4,
                                             uint32_t t8, uint64_t& r4, uint64_t& r8) {
@@ -210,7 +220,7 @@ __device__ __forceinline__ void masks_shift(uint32_t lo, uint32_t hi, int nq, ui
   for (int q = 15; q >= 0; --q) {
     if (FULL || q < nq) {
       uint32_t x0 = lo + (uint32_t)q, x1 = hi, x2 = t, x3 = ctr3;
-      philox4x32_10(x0, x1, x2, x3, k0, k1);
+      philox4x32_10<BUMP_SALU>(x0, x1, x2, x3, k0, k1);
       if (q >= 8)
         shift_in4(a4_hi, a8_hi, x0, x1, x2, x3, t4, t8);
       else

@@ -7,6 +7,14 @@
 
 #include "ising_device.hpp"
 
+// Pointer qualifier for read-only tables: the AMDGPU constant address space
+// in the device pass (scalar loads); the host pass never runs kernel code.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define ISING_CONSTANT_AS __attribute__((address_space(4)))
+#else
+#define ISING_CONSTANT_AS
+#endif
+
 namespace ising {
 
 // ---------------------------------------------------------------------
@@ -270,11 +278,14 @@ __device__ __forceinline__ int64_t wrap_row(int64_t y, int64_t L) {
 // One colour step of one lattice over the tiles first, first + stride, ...
 // of the tiled layout described above.  `colour` and `em` are uniform; the
 // callers pass constants where they can.  Ends with a block barrier.
-template <bool FULL, bool WIDE>
+template <bool FULL, int WIDEM, bool BUMP_SALU = false>
 __device__ __forceinline__ void sweep_tiles(const TileArgs& a, int colour, bool em,
                                             int64_t first, int64_t stride, uint64_t* tile,
                                             uint32_t& anti, uint32_t& up) {
   const Geom& g = a.g;
+  // WIDEM: 0 / 1 fixes the row-group shape at compile time, 2 reads it from
+  // the arguments (W >= 64).
+  const bool WIDE = WIDEM == 2 ? (g.W >= 64) : (WIDEM == 1);
   uint64_t* __restrict__ self = a.planes + (colour ? a.plane_words : 0);
   const uint64_t* __restrict__ other = a.planes + (colour ? 0 : a.plane_words);
   const int lane = threadIdx.x & 63;
@@ -315,7 +326,9 @@ __device__ __forceinline__ void sweep_tiles(const TileArgs& a, int colour, bool 
     for (int rr0 = wave * P; rr0 < SR; rr0 += 4 * P) {
       const int rr = rr0 + st_r;
       if (st_r >= 0 && rr < SR) {
-        const int64_t yy = wrap_row(y0 - 1 + rr, g.L);
+        // a tile may span more than L rows when L is small: full modulo
+        int64_t yy = (y0 - 1 + rr) % g.L;
+        yy = yy < 0 ? yy + g.L : yy;
         const int32_t ww = (int32_t)wrap_row(w0 - 1 + st_c, g.W);
         tile[rr * SW + st_c] = other[yy * g.W + ww];
         if (WIDE && lane < 2) {
@@ -356,7 +369,7 @@ __device__ __forceinline__ void sweep_tiles(const TileArgs& a, int colour, bool 
       }
       const int nq = (FULL || w < g.W - 1) ? 16 : (g.nb_last >> 2);
       uint64_t r4, r8;
-      masks_shift<FULL>(lo, hi, nq, a.k0, a.k1, a.t, ctr3, a.t4, a.t8, r4, r8);
+      masks_shift<FULL, BUMP_SALU>(lo, hi, nq, a.k0, a.k1, a.t, ctr3, a.t4, a.t8, r4, r8);
       const uint64_t valid = (FULL || w < g.W - 1) ? ~0ull : low_mask(g.nb_last);
       const uint64_t s_new = s ^ (flip_mask(s, n, r4, r8) & valid);
       self[y * g.W + w] = s_new;
@@ -378,7 +391,7 @@ __global__ __launch_bounds__(256) void k_tile_sweep(TileArgs a) {
   const int b = blockIdx.x;
   const int lb = (G % 8 == 0) ? (b % 8) * (G / 8) + b / 8 : b;
   uint32_t anti = 0, up = 0;
-  sweep_tiles<FULL, WIDE>(a, C, EM, lb, G, tile, anti, up);
+  sweep_tiles<FULL, WIDE ? 1 : 0>(a, C, EM, lb, G, tile, anti, up);
   if (C == 1 && EM) {
     block_sum2(anti, up, red);
     if (threadIdx.x == 0) {
@@ -392,6 +405,94 @@ __global__ __launch_bounds__(256) void k_finalize_em(const uint64_t* part, int n
                                                      int64_t* EM) {
   __shared__ uint64_t red64[8];
   finalize_partials(part, nblocks, L, EM, red64);
+}
+
+// ---------------------------------------------------------------------
+// Batched persistent kernel (many lattices of uneven size and temperature
+// in one launch).  Each workgroup walks its item list; for every item it
+// runs all n sweeps of its share of that lattice.  Between colour steps the
+// nwg workgroups of a lattice meet at an atomic counter (agent-scope
+// release/acquire, so the other colour's words written on any XCD are
+// visible); a lattice with one workgroup only needs the block barrier.
+// Waits are bounded by a wall-clock limit: on expiry the workgroup records
+// the failure in *err and leaves, so the grid always drains.
+// ---------------------------------------------------------------------
+__device__ __forceinline__ bool lattice_barrier(uint32_t* bar, uint32_t target, uint32_t* err,
+                                                uint64_t limit, int* flag) {
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    const uint64_t start = __builtin_amdgcn_s_memrealtime();
+    int ok = 1;
+    while (__hip_atomic_load(bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      __builtin_amdgcn_s_sleep(2);
+      if (__builtin_amdgcn_s_memrealtime() - start > limit) {
+        __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ok = 0;
+        break;
+      }
+    }
+    *flag = ok;
+  }
+  __syncthreads();
+  __threadfence();
+  return *flag != 0;
+}
+
+__device__ __forceinline__ bool run_lattice(const BatchLattice& Lt, int rank, int64_t n,
+                                            uint32_t* err, uint64_t limit, uint64_t* tile,
+                                            uint32_t* red, uint64_t* red64, int* flag) {
+  TileArgs a = Lt.ta;
+  const uint32_t t0 = Lt.ta.t;
+  const bool em = Lt.EM != nullptr;
+  const int nwg = Lt.nwg;
+  uint32_t arrivals = 0;
+  for (int64_t k = 0; k < n; ++k) {
+    a.t = t0 + (uint32_t)k;
+    uint32_t anti = 0, up = 0;
+    sweep_tiles<false, 2, true>(a, 0, false, rank, nwg, tile, anti, up);
+    if (nwg > 1 && !lattice_barrier(Lt.bar, (++arrivals) * (uint32_t)nwg, err, limit, flag))
+      return false;
+    sweep_tiles<false, 2, true>(a, 1, em, rank, nwg, tile, anti, up);
+    if (em) {
+      block_sum2(anti, up, red);
+      if (threadIdx.x == 0) {
+        if (nwg == 1) {
+          Lt.EM[2 * k] = 2 * (int64_t)anti - 2 * a.g.L * a.g.L;
+          Lt.EM[2 * k + 1] = 2 * (int64_t)up - a.g.L * a.g.L;
+        } else {
+          Lt.part[2 * rank] = anti;
+          Lt.part[2 * rank + 1] = up;
+        }
+      }
+      __syncthreads();
+    }
+    if (nwg > 1) {
+      if (!lattice_barrier(Lt.bar, (++arrivals) * (uint32_t)nwg, err, limit, flag)) return false;
+      if (em && rank == 0) finalize_partials(Lt.part, nwg, a.g.L, Lt.EM + 2 * k, red64);
+    }
+  }
+  return true;
+}
+
+__global__ __launch_bounds__(256) void k_batch(BatchArgs b) {
+  __shared__ uint64_t tile[kTileLdsMaxWords];
+  __shared__ uint64_t red64[8];
+  __shared__ uint32_t red[8];
+  __shared__ int flag;
+  // The tables are read-only for the whole launch: read them through the
+  // constant address space so that they land in SGPRs (scalar loads).
+  typedef const BatchWG ISING_CONSTANT_AS* WgPtr;
+  typedef const BatchItem ISING_CONSTANT_AS* ItemPtr;
+  typedef const BatchLattice ISING_CONSTANT_AS* LatPtr;
+  const BatchWG wg = ((WgPtr)b.wgs)[blockIdx.x];
+  for (int it = 0; it < wg.n_items; ++it) {
+    const BatchItem item = ((ItemPtr)b.items)[wg.first_item + it];
+    const BatchLattice Lt = ((LatPtr)b.lat)[item.lattice];
+    if (!run_lattice(Lt, item.rank, b.n, b.err, b.spin_limit, tile, red, red64, &flag))
+      return;
+  }
 }
 
 // ---------------------------------------------------------------------
@@ -429,6 +530,24 @@ hipError_t launch_finalize_em(hipStream_t st, const uint64_t* part, int blocks, 
   hipLaunchKernelGGL(k_finalize_em, dim3(1), dim3(256), 0, st, part, blocks, L, EM);
   return hipGetLastError();
 }
+hipError_t launch_batch(hipStream_t st, const BatchArgs& a, int blocks, bool cooperative) {
+  void* args[] = {(void*)&a};
+  const void* fn = (const void*)k_batch;
+  if (!cooperative) {
+    hipLaunchKernelGGL(k_batch, dim3(blocks), dim3(256), 0, st, a);
+    return hipGetLastError();
+  }
+  return hipLaunchCooperativeKernel(fn, dim3(blocks), dim3(256), args, 0, st);
+}
+
+int batch_max_blocks_per_cu() {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void*)k_batch, 256,
+                                                   0) != hipSuccess)
+    return 0;
+  return n;
+}
+
 hipError_t launch_init(hipStream_t st, uint64_t* planes, const Geom& g, uint32_t k0, uint32_t k1,
                        uint32_t sid4, int init, int blocks) {
   const bool aligned = (g.L % 8) == 0;

@@ -1,0 +1,115 @@
+"""Batched persistent kernel (ising_multi_sweep) parity.
+
+Every lattice advanced inside one fused launch must be bit-identical (spins
+and every per-sweep (E, M)) to the same lattice advanced alone with
+ising_sweep, and small members are also checked against the CPU oracle.
+Mixes cover single-workgroup packed lattices, lattices split over many
+workgroups with atomic barriers, partial last words (L % 128 != 0) and
+lattices the tiled layout does not cover (L % 8 != 0, plain fallback).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def I():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1007_3726_amd import ising
+    ising.lib()
+    return ising
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _make(I, specs):
+    lats = []
+    for (L, T, seed, sid, init) in specs:
+        lats.append(I.Lattice(L, seed=seed, stream_id=sid, init=init, beta=1.0 / T))
+    return lats
+
+
+def _batched_vs_plain(I, specs, n, chunks=1):
+    import torch
+    batch = _make(I, specs)
+    plain = _make(I, specs)
+    EMb = [torch.empty((n, 2), dtype=torch.int64, device="cuda") for _ in specs]
+    per = n // chunks
+    for c in range(chunks):
+        I.multi_sweep(batch, per, [e[c * per:(c + 1) * per] for e in EMb])
+    torch.cuda.synchronize()
+    for i, (lat_b, lat_p) in enumerate(zip(batch, plain)):
+        EMp = lat_p.sweep_em(n).cpu().numpy()
+        assert np.array_equal(EMb[i].cpu().numpy(), EMp), "E/M differ for lattice %d %r" % (
+            i, specs[i])
+        assert np.array_equal(lat_b.get_spins(), lat_p.get_spins()), "spins differ %r" % (
+            specs[i],)
+        assert lat_b.sweep_count == lat_p.sweep_count == n
+    return batch
+
+
+def test_mixed_sizes_match_plain(I):
+    H = workloads.INIT_HOT
+    specs = [(64, 2.2, 1, 0, H), (128, 2.25, 1, 1, H), (256, 2.3, 2, 2, H), (512, 2.27, 3, 3, H),
+             (1024, 2.269, 1, 4, H), (96, 3.0, 5, 5, H), (160, 1.8, 6, 6, workloads.INIT_COLD_UP),
+             (130, 2.4, 7, 7, H), (6, 2.0, 8, 8, H), (2048, 2.3, 9, 9, H)]
+    _say("case mixed sizes", [s[0] for s in specs])
+    _batched_vs_plain(I, specs, 24, chunks=2)
+
+
+def test_single_large_lattice_many_workgroups(I):
+    specs = [(4096, 2.269185, 11, 3, workloads.INIT_HOT)]
+    _say("case single 4096")
+    _batched_vs_plain(I, specs, 12)
+
+
+def test_wide_rows_and_partial_words(I):
+    H = workloads.INIT_HOT
+    specs = [(8192, 2.1, 1, 1, H), (8224, 2.5, 2, 2, H), (1000, 2.269, 3, 3, H),
+             (520, 2.3, 4, 4, H), (40, 2.0, 5, 5, H)]
+    _say("case wide and partial", [s[0] for s in specs])
+    _batched_vs_plain(I, specs, 6)
+
+
+def test_small_members_match_oracle(I):
+    import torch
+    H = workloads.INIT_HOT
+    specs = [(64, 2.269, 1, 0, H), (128, 2.5, 4, 2, H), (72, 1.9, 9, 1, workloads.INIT_COLD_DOWN)]
+    lats = _make(I, specs)
+    n = 30
+    EMs = [torch.empty((n, 2), dtype=torch.int64, device="cuda") for _ in specs]
+    I.multi_sweep(lats, n, EMs)
+    for (L, T, seed, sid, init), lat, em in zip(specs, lats, EMs):
+        s, oEM = oracle.run(L, 1.0 / T, seed, sid, init, n)
+        assert np.array_equal(em.cpu().numpy(), oEM)
+        assert np.array_equal(lat.get_spins(), s)
+
+
+def test_fss_grid_subset_matches_plain(I):
+    grid = workloads.fss_grid(sizes=[64, 128, 256, 512], temps=workloads.FSS_TEMPS[::8])
+    specs = [(g.L, g.T, g.seed, g.stream_id, g.init) for g in grid]
+    _say("case fss subset", len(specs))
+    _batched_vs_plain(I, specs, 40)
+
+
+def test_batched_errors(I):
+    a = I.Lattice(64, beta=0.4)
+    b = I.Lattice(64)
+    with pytest.raises(I.IsingError):
+        I.multi_sweep([a, b], 1)  # b has no beta
+    with pytest.raises(I.IsingError):
+        I.multi_sweep([a, a], 1)  # repeated handle
+    I.multi_sweep([], 3)
+    I.multi_sweep([a], 0)
+    assert a.sweep_count == 0
