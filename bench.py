@@ -44,7 +44,60 @@ def parse():
                    help="sweeps per step (default: the workload's 2000); for short profiles")
     p.add_argument("--copy-calibration", action="store_true",
                    help="also run a plain 1 GiB device copy, the reference for HBM counters")
+    p.add_argument("--no-batched", action="store_true",
+                   help="skip the batched finite-size-scaling grid")
+    p.add_argument("--batched-sweeps", type=int, default=workloads.FSS_SWEEPS)
     return p.parse_args()
+
+
+def binder_exact(M, discard):
+    """U4 = 1 - <M^4> / (3 <M^2>^2) from an int64 series, with exact integer sums."""
+    from fractions import Fraction
+    m = [int(v) for v in M[discard:]]
+    n = len(m)
+    s2 = sum(v * v for v in m)
+    s4 = sum(v ** 4 for v in m)
+    return float(1 - Fraction(s4 * n, 3 * s2 * s2)) if s2 else float("nan")
+
+
+def bench_batched(torch, ising, dev, sweeps):
+    """224 lattices (L in 64..4096 x 32 temperatures) in one persistent launch."""
+    grid = workloads.fss_grid()
+    lats = [ising.Lattice(g.L, seed=g.seed, stream_id=g.stream_id, init=g.init, beta=1.0 / g.T,
+                          device=dev) for g in grid]
+    EMs = [torch.empty((sweeps, 2), dtype=torch.int64, device=dev) for _ in grid]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ising.multi_sweep(lats, sweeps, EMs)  # synchronises
+    dt = time.perf_counter() - t0
+    updates = sum(g.L * g.L for g in grid) * sweeps
+    discard = min(workloads.FSS_DISCARD, sweeps // 5)
+    binder = {}
+    for g, em in zip(grid, EMs):
+        binder.setdefault(g.L, []).append(binder_exact(em[:, 1].cpu().numpy(), discard))
+    # the same lattices advanced one by one with the plain path (rate sample)
+    plain_sweeps = max(1, min(sweeps, 500))
+    seq = [ising.Lattice(g.L, seed=g.seed, stream_id=g.stream_id, init=g.init, beta=1.0 / g.T,
+                         device=dev) for g in grid]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for lat, em in zip(seq, EMs):
+        lat.sweep(plain_sweeps, em[:plain_sweeps])
+    torch.cuda.synchronize()
+    dt_plain = time.perf_counter() - t1
+    plain_updates = sum(g.L * g.L for g in grid) * plain_sweeps
+    tidx = [0, len(workloads.FSS_TEMPS) // 2, len(workloads.FSS_TEMPS) - 1]
+    return {
+        "value": round(updates / (dt * 1e9), 2), "unit": "spin updates/ns",
+        "workload": "224 lattices, L in {64..4096} x 32 T in [2.20, 2.34], hot start, "
+                    "%d sweeps each, per-sweep int64 E/M, one persistent launch" % sweeps,
+        "seconds": round(dt, 3),
+        "plain_one_by_one": {"value": round(plain_updates / (dt_plain * 1e9), 2),
+                             "sweeps": plain_sweeps},
+        "binder_U4": {str(L): {"%.4f" % workloads.FSS_TEMPS[i]: round(v[i], 4) for i in tidx}
+                      for L, v in binder.items()},
+        "discard": discard,
+    }
 
 
 def cpu_baseline(w, sweeps):
@@ -136,6 +189,11 @@ def main():
         torch.cuda.synchronize()
         result["copy_calibration_bytes"] = 1 << 30
         del src, dst
+    if not args.no_batched:
+        print("bench: batched FSS grid (%d sweeps)" % args.batched_sweeps, file=sys.stderr,
+              flush=True)
+        del EM
+        result["batched"] = bench_batched(torch, ising, dev, args.batched_sweeps)
     if not args.no_cpu_baseline:
         print("bench: CPU oracle baseline (%d sweeps)" % args.cpu_sweeps, file=sys.stderr,
               flush=True)

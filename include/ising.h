@@ -142,15 +142,40 @@ ISING_API ising_status ising_set_sweep(ising_t *h, uint64_t t);
 ISING_API ising_status ising_get_info(const ising_t *h, int64_t *L, int64_t *words_per_row, void **planes);
 
 /*
- * Batched sweeps: enqueue n sweeps on each of the `count` handles (all
- * created on the same device and stream, each with a beta set) in one
- * persistent fused kernel launch, equivalent bit for bit to calling
- * ising_sweep(hs[i], n, dev_EM[i]) on each.  dev_EM may be NULL or hold
- * NULL entries.  Each handle's counter advances by n.
- * Errors: EINVAL, ERANGE, EDEVICE.
+ * Batched sweeps: n sweeps on each of the `count` handles (all created on
+ * the same device and stream, each with a beta set, no handle twice),
+ * equivalent bit for bit to calling ising_sweep(hs[i], n, dev_EM[i]) on
+ * each.  All lattices advance together in fused launches (or, for batches
+ * of small lattices, one persistent launch); see ising_multi_sweep_form.
+ * dev_EM may be NULL or hold NULL entries.  Each handle's counter advances
+ * by n.  Synchronises the stream.  Errors: EINVAL, ERANGE, EDEVICE.
  */
 ISING_API ising_status ising_multi_sweep(ising_t *const *hs, int32_t count, int64_t n,
                                int64_t *const *dev_EM);
+
+/*
+ * Same as ising_multi_sweep with the launch form chosen by the caller:
+ * form -1 lets the cost model choose, 0 forces the fused form (two launches
+ * per sweep over the flattened tiles of all lattices, replayed from captured
+ * hipGraph chunks of graph_chunk sweeps; 0 disables graphs, -1 keeps the
+ * default), 1 forces the packed persistent form (each lattice on one
+ * workgroup, one launch for all n sweeps).  Results are bit-identical for
+ * every form.  For tests and tuning.
+ */
+ISING_API ising_status ising_multi_sweep_form(ising_t *const *hs, int32_t count, int64_t n,
+                                              int64_t *const *dev_EM, int32_t form,
+                                              int32_t graph_chunk);
+
+/*
+ * Launch form the batched path would choose for lattices of sides Ls[i]
+ * (each a multiple of 8) on a device with `cus` compute units: *form_out
+ * 0 (fused) or 1 (packed), *blocks_out its grid size, *est_seconds_out
+ * (may be NULL) the cost model's seconds per sweep.  Host-only; for
+ * inspection and tests.
+ */
+ISING_API ising_status ising_batch_plan(const int64_t *Ls, int32_t count, int32_t cus,
+                                        int32_t *form_out, int32_t *blocks_out,
+                                        double *est_seconds_out);
 
 /* ---------------------------------------------------------------- */
 /* Served mode: continuous batching of independent simulations.      */

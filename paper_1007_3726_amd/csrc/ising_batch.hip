@@ -1,21 +1,22 @@
-// Batched sweeps: many lattices of uneven size and temperature advanced by
-// one persistent fused kernel launch (k_batch).
+// Batched sweeps: many lattices of uneven size and temperature.
 //
-// Host side:
-//   * plan_batch (the autotuner's cost model) assigns workgroups to
-//     lattices: a lattice whose work per sweep exceeds the per-workgroup
-//     share gets k workgroups (tile shares rank, rank + k, ... and an atomic
-//     barrier between colour steps); smaller lattices are packed, longest
-//     first, onto single workgroups that run them one after the other;
-//   * the workgroups of one lattice are placed on one XCD where possible
-//     (block b runs on XCD b mod 8), so the lattice stays in one L2;
-//   * the task tables are uploaded into a library-owned device buffer and
-//     the kernel is launched cooperatively (all workgroups co-resident).
+// Two launch forms, chosen per call by the cost model of the autotuner
+// (ising_tune.hip):
+//   * fused: the tiles of all lattices form one flat list; each sweep is
+//     two launches of k_fused (colour 0, colour 1) that walk the whole list,
+//     so every colour step is balanced over the whole GPU.  Long runs are
+//     replayed from a captured hipGraph chunk of K sweeps (a device-side
+//     sweep counter advanced by the last node keeps the chunk reusable);
+//   * packed: when every lattice is small, lattices are packed (longest
+//     first) onto workgroups of one persistent launch (k_batch) that runs all
+//     n sweeps with block barriers only.
 // Lattices the tiled layout does not cover (L % 8 != 0, or Philox block
 // indices crossing 2^32 inside a row) are advanced with the plain path.
+// The task tables live in a library-owned device buffer per device.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <mutex>
 #include <numeric>
@@ -34,7 +35,8 @@ struct DeviceTable {
   std::mutex m;
   void* ptr = nullptr;
   size_t cap = 0;
-  int capacity_blocks = 0;  // co-resident k_batch workgroups
+  int cus = 0;
+  hipStream_t capture = nullptr;  // private stream for graph capture
 };
 
 DeviceTable& table_for(int device) {
@@ -44,133 +46,220 @@ DeviceTable& table_for(int device) {
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
+ising_status ensure_table(DeviceTable& T, size_t bytes) {
+  if (T.cap >= bytes) return ISING_OK;
+  if (T.ptr) hipFree(T.ptr);
+  T.ptr = nullptr;
+  T.cap = 0;
+  const size_t want = std::max<size_t>(bytes * 2, 1 << 20);
+  hipError_t e = hipMalloc(&T.ptr, want);
+  if (e != hipSuccess) return hip_fail(e, "batched sweeps: table allocation");
+  T.cap = want;
+  return ISING_OK;
+}
+
+int cu_count(DeviceTable& T, int device) {
+  if (T.cus == 0) {
+    hipDeviceProp_t p;
+    if (hipGetDeviceProperties(&p, device) == hipSuccess) T.cus = p.multiProcessorCount;
+  }
+  return T.cus;
+}
+
 }  // namespace
 
-int batch_capacity(int device) {
-  DeviceTable& t = table_for(device);
-  if (t.capacity_blocks == 0) {
-    hipDeviceProp_t p;
-    if (hipGetDeviceProperties(&p, device) != hipSuccess) return 0;
-    const int per_cu = batch_max_blocks_per_cu();
-    t.capacity_blocks = per_cu * p.multiProcessorCount;
-  }
-  return t.capacity_blocks;
-}
-
-// Cost model (seconds per sweep) used to compare plans: a workgroup
-// updates about `wg_rate` spins per second; a multi-workgroup lattice pays
-// two barriers per sweep.
-BatchPlan plan_batch(const std::vector<int64_t>& work, const std::vector<int64_t>& max_wg,
-                     int capacity, const PlanModel& model) {
-  const int count = (int)work.size();
-  const double total = std::accumulate(work.begin(), work.end(), 0.0);
-  BatchPlan best;
-  best.est_seconds = 1e300;
-  if (count == 0 || capacity <= 0) return best;
-  const double scales[] = {0.7, 0.85, 1.0, 1.2, 1.5, 2.0, 3.0};
-  std::vector<int> order(count);
+// Pack single-workgroup lattices onto `bins` workgroups, longest first.
+std::vector<std::vector<int>> pack_lpt(const std::vector<double>& cost, int bins) {
+  std::vector<int> order(cost.size());
   std::iota(order.begin(), order.end(), 0);
-  std::sort(order.begin(), order.end(), [&](int a, int b) { return work[a] > work[b]; });
-  for (double sc : scales) {
-    const int target_wg = std::max(1, (int)(capacity / sc));
-    const double share = total / target_wg;
-    BatchPlan p;
-    p.nwg.assign(count, 1);
-    std::vector<int> small;
-    int used = 0;
-    for (int i : order) {
-      int k = 1;
-      if ((double)work[i] > 1.5 * share) {
-        k = (int)std::llround((double)work[i] / share);
-        k = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)k, max_wg[i], capacity}));
-      }
-      if (k > 1) {
-        p.nwg[i] = k;
-        used += k;
-      } else {
-        small.push_back(i);  // one workgroup: packed with the other small lattices
-      }
-    }
-    int bins = capacity - used;
-    if (bins < 1 && !small.empty()) continue;
-    // pack small lattices onto single workgroups, longest first
-    bins = std::min<int>(bins, (int)small.size());
-    std::vector<double> load(bins, 0.0);
-    p.packs.assign(bins, {});
-    for (int i : small) {
-      int b = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-      load[b] += (double)work[i];
-      p.packs[b].push_back(i);
-    }
-    double est = 0.0;
-    for (int i = 0; i < count; ++i)
-      if (p.nwg[i] > 1)
-        est = std::max(est, (double)work[i] / p.nwg[i] / model.wg_rate + 2 * model.barrier_s);
-    for (double l : load) est = std::max(est, l / model.wg_rate);
-    p.blocks = used + bins;
-    p.est_seconds = est;
-    if (est < best.est_seconds) best = p;
+  std::sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+  bins = std::max(1, std::min<int>(bins, (int)cost.size()));
+  std::vector<std::vector<int>> packs(bins);
+  std::vector<double> load(bins, 0.0);
+  for (int i : order) {
+    const int b = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    load[b] += cost[i];
+    packs[b].push_back(i);
   }
-  return best;
+  return packs;
 }
 
-// Block indices for the plan: the workgroups of a multi-workgroup lattice
-// go to one XCD (block b -> XCD b mod 8) when they fit.  Returns, per block,
-// the list of (lattice, rank) items.
-static std::vector<std::vector<BatchItem>> place_blocks(const BatchPlan& p, int count) {
-  const int G = p.blocks;
-  const int nx = 8;
-  std::vector<std::vector<int>> free_slots(nx);  // block indices per XCD
-  for (int b = 0; b < G; ++b) free_slots[b % nx].push_back(b);
-  for (auto& v : free_slots) std::reverse(v.begin(), v.end());
-  std::vector<std::vector<BatchItem>> blocks(G);
-  std::vector<int> big;
-  for (int i = 0; i < count; ++i)
-    if (p.nwg[i] > 1) big.push_back(i);
-  std::sort(big.begin(), big.end(), [&](int a, int b) { return p.nwg[a] > p.nwg[b]; });
-  for (int i : big) {
-    int rank = 0;
-    while (rank < p.nwg[i]) {
-      int x = 0;
-      for (int j = 1; j < nx; ++j)
-        if (free_slots[j].size() > free_slots[x].size()) x = j;
-      while (rank < p.nwg[i] && !free_slots[x].empty()) {
-        const int b = free_slots[x].back();
-        free_slots[x].pop_back();
-        blocks[b].push_back(BatchItem{i, rank++});
-      }
-    }
+BatchPlan plan_batch(const std::vector<int64_t>& tiles, int cus, const PlanModel& m) {
+  BatchPlan p;
+  const int count = (int)tiles.size();
+  const int64_t total = std::accumulate(tiles.begin(), tiles.end(), (int64_t)0);
+  // fused: two launches per sweep, each walking all tiles with the full grid
+  p.fused_blocks = (int)std::min<int64_t>(std::max<int64_t>(total, 1), (int64_t)m.wg_per_cu * cus);
+  const double rounds = std::ceil((double)total / p.fused_blocks);
+  p.fused_s = 2.0 * (m.launch_gap_s + rounds * m.tile_s_full);
+  // packed: one workgroup per bin, all sweeps in one launch
+  const int bins = std::min<int>(count, m.wg_per_cu * cus);
+  std::vector<double> cost(count);
+  for (int i = 0; i < count; ++i) cost[i] = (double)tiles[i];
+  p.packs = pack_lpt(cost, bins);
+  double worst = 0.0;
+  for (const auto& pk : p.packs) {
+    double s = 0.0;
+    for (int i : pk) s += cost[i];
+    worst = std::max(worst, s);
   }
-  int x = 0;
-  for (const auto& pack : p.packs) {
-    for (int j = 0; j < nx && free_slots[x].empty(); ++j) x = (x + 1) % nx;
-    const int b = free_slots[x].back();
-    free_slots[x].pop_back();
-    for (int i : pack) blocks[b].push_back(BatchItem{i, 0});
-    x = (x + 1) % nx;
-  }
-  return blocks;
+  const double per_cu = std::ceil((double)p.packs.size() / std::max(cus, 1));
+  const double tile_s = std::max(m.tile_s_alone, m.tile_s_full * per_cu / m.wg_per_cu);
+  p.packed_s = 2.0 * worst * tile_s;
+  p.packed = p.packed_s < p.fused_s;
+  return p;
 }
 
-PlanModel default_model() {
-  PlanModel m;
-  m.wg_rate = 1.1e9;     // spins per second per workgroup at 8 workgroups per CU
-  m.barrier_s = 6e-6;    // one lattice barrier
-  return m;
+static ising_status run_fused(ising_lattice* const* hs, const std::vector<int>& idx,
+                              const std::vector<TileArgs>& targs, int64_t n,
+                              int64_t* const* dev_EM, const BatchOptions& opt, DeviceTable& T,
+                              int blocks) {
+  hipStream_t stream = hs[idx[0]]->stream;
+  const int nl = (int)idx.size();
+  std::vector<FusedLattice> lat(nl);
+  std::vector<FusedTile> tiles;
+  bool any_em = false;
+  for (int j = 0; j < nl; ++j) {
+    const int i = idx[j];
+    FusedLattice& F = lat[j];
+    std::memset(&F, 0, sizeof(F));
+    F.ta = targs[i];
+    F.ta.t = (uint32_t)hs[i]->sweep;
+    F.EM = dev_EM ? dev_EM[i] : nullptr;
+    any_em = any_em || F.EM != nullptr;
+    F.first_tile = (int64_t)tiles.size();
+    F.ntiles = F.ta.tiles;
+    for (int64_t t = 0; t < F.ntiles; ++t) tiles.push_back(FusedTile{j, (int32_t)t});
+  }
+  const int64_t ntiles = (int64_t)tiles.size();
+  const size_t off_k = 0;
+  const size_t off_lat = 256;
+  const size_t off_tiles = align_up(off_lat + nl * sizeof(FusedLattice), 256);
+  const size_t off_part = align_up(off_tiles + ntiles * sizeof(FusedTile), 256);
+  const size_t bytes = align_up(off_part + 2 * 2 * (size_t)ntiles * sizeof(uint32_t), 256);
+  ising_status st = ensure_table(T, bytes);
+  if (st != ISING_OK) return st;
+  char* d = (char*)T.ptr;
+  std::vector<char> img(off_part, 0);
+  std::memcpy(img.data() + off_lat, lat.data(), nl * sizeof(FusedLattice));
+  std::memcpy(img.data() + off_tiles, tiles.data(), ntiles * sizeof(FusedTile));
+  hipError_t e = hipMemcpyAsync(d, img.data(), img.size(), hipMemcpyHostToDevice, stream);
+  if (e != hipSuccess) return hip_fail(e, "batched sweeps: table upload");
+
+  FusedArgs f;
+  f.lat = (const FusedLattice*)(d + off_lat);
+  f.nlat = nl;
+  f.klocal = 0;
+  f.tiles = (const FusedTile*)(d + off_tiles);
+  f.ntiles = ntiles;
+  f.kbase = (const uint32_t*)(d + off_k);
+  f.part = (uint32_t*)(d + off_part);
+  uint32_t* kbase = (uint32_t*)(d + off_k);
+
+  int64_t done = 0;
+  const int K = opt.graph_chunk;
+  if (K > 0 && n >= 2 * (int64_t)K) {
+    // capture K sweeps (+ the counter advance) once on a private stream,
+    // then replay the chunk n / K times on the caller's stream
+    if (!T.capture) {
+      e = hipStreamCreateWithFlags(&T.capture, hipStreamNonBlocking);
+      if (e != hipSuccess) return hip_fail(e, "batched sweeps: capture stream");
+    }
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    e = hipStreamBeginCapture(T.capture, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      for (int k = 0; k < K && e == hipSuccess; ++k) {
+        f.klocal = k;
+        e = launch_fused(T.capture, 0, f, blocks);
+        if (e == hipSuccess) e = launch_fused(T.capture, 1, f, blocks);
+      }
+      if (e == hipSuccess) e = launch_advance(T.capture, kbase, (uint32_t)K);
+      hipError_t e2 = hipStreamEndCapture(T.capture, &graph);
+      if (e == hipSuccess) e = e2;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    const int64_t reps = n / K;
+    for (int64_t r = 0; r < reps && e == hipSuccess; ++r) e = hipGraphLaunch(exec, stream);
+    // the executable graph may be destroyed once its launches are enqueued
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (exec) hipGraphExecDestroy(exec);
+    if (graph) hipGraphDestroy(graph);
+    if (e != hipSuccess) return hip_fail(e, "batched sweeps: graph capture/replay");
+    done = reps * K;
+  }
+  // remaining sweeps: direct launches at kbase + klocal
+  for (int64_t k = 0; k < n - done; ++k) {
+    f.klocal = (int32_t)k;
+    e = launch_fused(stream, 0, f, blocks);
+    if (e == hipSuccess) e = launch_fused(stream, 1, f, blocks);
+    if (e != hipSuccess) return hip_fail(e, "batched sweeps: fused launch");
+  }
+  if (any_em) {
+    f.klocal = (int32_t)(n - done) - 1;  // the last sweep: kbase + klocal = n - 1
+    e = launch_fused_finalize(stream, f, std::min(nl, 1024));
+    if (e != hipSuccess) return hip_fail(e, "batched sweeps: finalize launch");
+  }
+  e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return hip_fail(e, "batched sweeps: synchronize");
+  return ISING_OK;
+}
+
+static ising_status run_packed(ising_lattice* const* hs, const std::vector<int>& idx,
+                               const std::vector<TileArgs>& targs, int64_t n,
+                               int64_t* const* dev_EM, const BatchPlan& plan, DeviceTable& T) {
+  hipStream_t stream = hs[idx[0]]->stream;
+  const int nl = (int)idx.size();
+  std::vector<BatchLattice> lat(nl);
+  for (int j = 0; j < nl; ++j) {
+    const int i = idx[j];
+    std::memset(&lat[j], 0, sizeof(BatchLattice));
+    lat[j].ta = targs[i];
+    lat[j].ta.t = (uint32_t)hs[i]->sweep;
+    lat[j].EM = dev_EM ? dev_EM[i] : nullptr;
+  }
+  std::vector<BatchWG> wgs(plan.packs.size());
+  std::vector<BatchItem> items;
+  for (size_t b = 0; b < plan.packs.size(); ++b) {
+    wgs[b].first_item = (int32_t)items.size();
+    wgs[b].n_items = (int32_t)plan.packs[b].size();
+    for (int j : plan.packs[b]) items.push_back(BatchItem{j, 0});
+  }
+  const size_t off_lat = 0;
+  const size_t off_items = align_up(nl * sizeof(BatchLattice), 256);
+  const size_t off_wgs = align_up(off_items + items.size() * sizeof(BatchItem), 256);
+  const size_t bytes = align_up(off_wgs + wgs.size() * sizeof(BatchWG), 256);
+  ising_status st = ensure_table(T, bytes);
+  if (st != ISING_OK) return st;
+  std::vector<char> img(bytes, 0);
+  std::memcpy(img.data() + off_lat, lat.data(), nl * sizeof(BatchLattice));
+  std::memcpy(img.data() + off_items, items.data(), items.size() * sizeof(BatchItem));
+  std::memcpy(img.data() + off_wgs, wgs.data(), wgs.size() * sizeof(BatchWG));
+  char* d = (char*)T.ptr;
+  hipError_t e = hipMemcpyAsync(d, img.data(), img.size(), hipMemcpyHostToDevice, stream);
+  if (e != hipSuccess) return hip_fail(e, "batched sweeps: table upload");
+  BatchArgs a;
+  a.lat = (const BatchLattice*)(d + off_lat);
+  a.items = (const BatchItem*)(d + off_items);
+  a.wgs = (const BatchWG*)(d + off_wgs);
+  a.n = n;
+  e = launch_batch(stream, a, (int)wgs.size());
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return hip_fail(e, "batched sweeps: packed launch");
+  return ISING_OK;
 }
 
 ising_status batch_sweeps(ising_lattice* const* hs, int32_t count, int64_t n,
-                          int64_t* const* dev_EM, const BatchOptions& opt) {
+                          int64_t* const* dev_EM, const BatchOptions& opt, int* form_out) {
+  if (form_out) *form_out = -1;
   if (count == 0 || n == 0) return ISING_OK;
-  hipStream_t stream = hs[0]->stream;
   const int device = hs[0]->device;
-  // split off lattices the tiled layout does not cover
   std::vector<int> tiled, other;
   std::vector<TileArgs> targs(count);
   for (int i = 0; i < count; ++i) {
     TileArgs ta;
     if (tile_args(hs[i], &ta)) {
-      ta.RPW = 1;  // finest tiles: most workgroups can share a lattice
+      ta.RPW = 1;  // finest tiles balance best across the flat list
       const int64_t TR = 4 * (int64_t)ta.R;
       ta.tiles = ((hs[i]->L + TR - 1) / TR) * ta.segs;
       targs[i] = ta;
@@ -184,117 +273,80 @@ ising_status batch_sweeps(ising_lattice* const* hs, int32_t count, int64_t n,
     if (st != ISING_OK) return st;
   }
   if (tiled.empty()) return ISING_OK;
-
-  const int cap = opt.max_blocks > 0 ? std::min(opt.max_blocks, batch_capacity(device))
-                                     : batch_capacity(device);
-  if (cap <= 0) return fail(ISING_EDEVICE, "ising_multi_sweep: cannot size the persistent grid");
-  std::vector<int64_t> work, max_wg;
-  for (int i : tiled) {
-    work.push_back(hs[i]->L * hs[i]->L);
-    max_wg.push_back(std::min<int64_t>(targs[i].tiles, kMaxBatchLatticeBlocks));
-  }
-  const BatchPlan plan = plan_batch(work, max_wg, cap, opt.model);
-  if (plan.blocks <= 0) return fail(ISING_EDEVICE, "ising_multi_sweep: no feasible plan");
-  const auto blocks = place_blocks(plan, (int)tiled.size());
-
-  // host image of the device tables
-  const int nl = (int)tiled.size();
-  size_t n_items = 0;
-  for (const auto& b : blocks) n_items += b.size();
-  size_t n_part = 0;
-  for (int j = 0; j < nl; ++j) n_part += (plan.nwg[j] > 1) ? 2 * (size_t)plan.nwg[j] : 0;
-  const size_t off_err = 0;
-  const size_t off_lat = 256;
-  const size_t off_items = align_up(off_lat + nl * sizeof(BatchLattice), 256);
-  const size_t off_wgs = align_up(off_items + n_items * sizeof(BatchItem), 256);
-  const size_t off_bar = align_up(off_wgs + blocks.size() * sizeof(BatchWG), 256);
-  const size_t off_part = align_up(off_bar + nl * sizeof(uint32_t), 256);
-  const size_t bytes = align_up(off_part + n_part * sizeof(uint64_t), 256);
-
   DeviceTable& T = table_for(device);
   std::lock_guard<std::mutex> lock(T.m);
-  if (T.cap < bytes) {
-    if (T.ptr) hipFree(T.ptr);
-    T.ptr = nullptr;
-    T.cap = 0;
-    hipError_t e = hipMalloc(&T.ptr, bytes * 2);
-    if (e != hipSuccess) return hip_fail(e, "ising_multi_sweep: table allocation");
-    T.cap = bytes * 2;
-  }
-  char* dbase = (char*)T.ptr;
-  std::vector<char> img(off_part, 0);  // partials need no initial value
-  std::vector<BatchLattice> lat(nl);
-  size_t part_at = 0;
-  for (int j = 0; j < nl; ++j) {
-    const int i = tiled[j];
-    BatchLattice& B = lat[j];
-    std::memset(&B, 0, sizeof(B));
-    B.ta = targs[i];
-    B.ta.t = (uint32_t)hs[i]->sweep;
-    B.EM = dev_EM ? dev_EM[i] : nullptr;
-    B.nwg = plan.nwg[j];
-    B.bar = (uint32_t*)(dbase + off_bar) + j;
-    if (B.nwg > 1) {
-      B.part = (uint64_t*)(dbase + off_part) + part_at;
-      part_at += 2 * (size_t)B.nwg;
-    }
-    B.full = hs[i]->g.nb_last == 64;
-    B.wide = hs[i]->g.W >= 64;
-  }
-  std::memcpy(img.data() + off_lat, lat.data(), nl * sizeof(BatchLattice));
-  std::vector<BatchWG> wgs(blocks.size());
-  {
-    size_t at = 0;
-    BatchItem* items = (BatchItem*)(img.data() + off_items);
-    for (size_t b = 0; b < blocks.size(); ++b) {
-      wgs[b].first_item = (int32_t)at;
-      wgs[b].n_items = (int32_t)blocks[b].size();
-      for (const BatchItem& it : blocks[b]) items[at++] = it;
-    }
-  }
-  std::memcpy(img.data() + off_wgs, wgs.data(), wgs.size() * sizeof(BatchWG));
-  hipError_t e = hipMemcpyAsync(T.ptr, img.data(), img.size(), hipMemcpyHostToDevice, stream);
-  if (e != hipSuccess) return hip_fail(e, "ising_multi_sweep: table upload");
-
-  BatchArgs a;
-  a.lat = (const BatchLattice*)(dbase + off_lat);
-  a.items = (const BatchItem*)(dbase + off_items);
-  a.wgs = (const BatchWG*)(dbase + off_wgs);
-  a.n = n;
-  a.err = (uint32_t*)(dbase + off_err);
-  a.spin_limit = (uint64_t)(opt.barrier_timeout_s * 1e8);
-  e = launch_batch(stream, a, (int)blocks.size(), opt.cooperative);
-  if (e != hipSuccess) return hip_fail(e, "ising_multi_sweep: persistent kernel launch");
-  uint32_t err = 0;
-  e = hipMemcpyAsync(&err, a.err, sizeof(err), hipMemcpyDeviceToHost, stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(stream);
-  if (e != hipSuccess) return hip_fail(e, "ising_multi_sweep: synchronize");
-  if (err)
-    return fail(ISING_EDEVICE,
-                "ising_multi_sweep: a lattice barrier timed out (workgroups not co-resident)");
-  return ISING_OK;
+  const int cus = cu_count(T, device);
+  if (cus <= 0) return fail(ISING_EDEVICE, "batched sweeps: no device properties");
+  std::vector<int64_t> tiles;
+  for (int i : tiled) tiles.push_back(targs[i].tiles);
+  const BatchPlan plan = plan_batch(tiles, cus, opt.model);
+  bool packed = plan.packed;
+  if (opt.force_form == 0) packed = false;
+  if (opt.force_form == 1) packed = true;
+  if (form_out) *form_out = packed ? 1 : 0;
+  if (packed) return run_packed(hs, tiled, targs, n, dev_EM, plan, T);
+  return run_fused(hs, tiled, targs, n, dev_EM, opt, T, plan.fused_blocks);
 }
 
 }  // namespace ising
 
 using namespace ising;
 
+extern "C" ising_status ising_batch_plan(const int64_t* Ls, int32_t count, int32_t cus,
+                                         int32_t* form_out, int32_t* blocks_out,
+                                         double* est_seconds_out) {
+  clear_error();
+  if (!Ls || count < 1 || cus < 1 || !form_out || !blocks_out)
+    return fail(ISING_EINVAL, "ising_batch_plan: bad arguments");
+  std::vector<int64_t> tiles(count);
+  for (int32_t i = 0; i < count; ++i) {
+    const int64_t L = Ls[i];
+    if (L < 8 || L % 8 || L > kMaxL)
+      return fail(ISING_EINVAL, "ising_batch_plan: L=%lld is not a tiled size", (long long)L);
+    const int64_t W = words_per_row(L);
+    const int64_t R = W >= 64 ? 1 : 64 / W;
+    const int64_t segs = W >= 64 ? (W + 63) / 64 : 1;
+    tiles[i] = ((L + 4 * R - 1) / (4 * R)) * segs;
+  }
+  const BatchPlan plan = plan_batch(tiles, cus, default_model());
+  *form_out = plan.packed ? 1 : 0;
+  *blocks_out = plan.packed ? (int32_t)plan.packs.size() : plan.fused_blocks;
+  if (est_seconds_out) *est_seconds_out = plan.packed ? plan.packed_s : plan.fused_s;
+  return ISING_OK;
+}
+
+static ising_status check_batch(ising_t* const* hs, int32_t count, int64_t n, const char* who) {
+  if (!hs || count < 0 || n < 0) return fail(ISING_EINVAL, "%s: bad arguments", who);
+  for (int32_t i = 0; i < count; ++i) {
+    if (!hs[i]) return fail(ISING_EINVAL, "%s: NULL handle %d", who, i);
+    if (!hs[i]->beta_set) return fail(ISING_EINVAL, "%s: handle %d has no beta", who, i);
+    if (hs[i]->sweep + (uint64_t)n > (1ull << 32))
+      return fail(ISING_ERANGE, "%s: counter overflow on handle %d", who, i);
+    if (hs[i]->stream != hs[0]->stream || hs[i]->device != hs[0]->device)
+      return fail(ISING_EINVAL, "%s: handles must share one device and stream", who);
+    for (int32_t j = 0; j < i; ++j)
+      if (hs[j] == hs[i]) return fail(ISING_EINVAL, "%s: handle %d repeated", who, i);
+  }
+  return ISING_OK;
+}
+
 extern "C" ising_status ising_multi_sweep(ising_t* const* hs, int32_t count, int64_t n,
                                           int64_t* const* dev_EM) {
+  return ising_multi_sweep_form(hs, count, n, dev_EM, -1, -1);
+}
+
+extern "C" ising_status ising_multi_sweep_form(ising_t* const* hs, int32_t count, int64_t n,
+                                               int64_t* const* dev_EM, int32_t form,
+                                               int32_t graph_chunk) {
   clear_error();
-  if (!hs || count < 0 || n < 0) return fail(ISING_EINVAL, "ising_multi_sweep: bad arguments");
-  for (int32_t i = 0; i < count; ++i) {
-    if (!hs[i]) return fail(ISING_EINVAL, "ising_multi_sweep: NULL handle %d", i);
-    if (!hs[i]->beta_set) return fail(ISING_EINVAL, "ising_multi_sweep: handle %d has no beta", i);
-    if (hs[i]->sweep + (uint64_t)n > (1ull << 32))
-      return fail(ISING_ERANGE, "ising_multi_sweep: counter overflow on handle %d", i);
-    if (hs[i]->stream != hs[0]->stream || hs[i]->device != hs[0]->device)
-      return fail(ISING_EINVAL, "ising_multi_sweep: handles must share one device and stream");
-    for (int32_t j = 0; j < i; ++j)
-      if (hs[j] == hs[i]) return fail(ISING_EINVAL, "ising_multi_sweep: handle %d repeated", i);
-  }
+  ising_status st = check_batch(hs, count, n, "ising_multi_sweep");
+  if (st != ISING_OK) return st;
+  if (form < -1 || form > 1 || graph_chunk < -1)
+    return fail(ISING_EINVAL, "ising_multi_sweep: bad form or graph chunk");
   BatchOptions opt = default_batch_options();
-  ising_status st = batch_sweeps(hs, count, n, dev_EM, opt);
+  opt.force_form = form;
+  if (graph_chunk >= 0) opt.graph_chunk = graph_chunk;
+  st = batch_sweeps(hs, count, n, dev_EM, opt, nullptr);
   if (st != ISING_OK) return st;
   for (int32_t i = 0; i < count; ++i) hs[i]->sweep += (uint64_t)n;
   return ISING_OK;

@@ -9,34 +9,32 @@
 
 namespace ising {
 
-// A lattice never gets more than this many workgroups in a batch.
-constexpr int kMaxBatchLatticeBlocks = 2048;
-
+// Cost model of the batched launch forms (filled by the autotuner defaults).
 struct PlanModel {
-  double wg_rate;    // spins per second one workgroup updates
-  double barrier_s;  // cost of one lattice barrier
+  int wg_per_cu;        // resident workgroups per CU for the tiled kernels
+  double tile_s_full;   // seconds per tile per workgroup with every CU fully occupied
+  double tile_s_alone;  // seconds per tile for a workgroup with its CU to itself
+  double launch_gap_s;  // gap between dependent launches
 };
 
 struct BatchPlan {
-  std::vector<int> nwg;                 // workgroups per lattice (1 = packed)
-  std::vector<std::vector<int>> packs;  // single workgroups running several small lattices
-  int blocks = 0;                       // grid size
-  double est_seconds = 0.0;             // model estimate per sweep
+  int fused_blocks = 0;                 // grid of the fused launches
+  double fused_s = 0.0;                 // model: seconds per sweep, fused form
+  std::vector<std::vector<int>> packs;  // packed form: lattices per workgroup
+  double packed_s = 0.0;                // model: seconds per sweep, packed form
+  bool packed = false;                  // the cheaper form
 };
 
 struct BatchOptions {
   PlanModel model;
-  int max_blocks;            // 0: occupancy-limited capacity of the device
-  bool cooperative;          // cooperative launch (co-residency guaranteed)
-  double barrier_timeout_s;  // a lattice barrier wait longer than this aborts the launch
+  int force_form;   // -1: cost model, 0: fused, 1: packed
+  int graph_chunk;  // sweeps per captured hipGraph chunk (0: no graph)
 };
 
 PlanModel default_model();
 BatchOptions default_batch_options();
-int batch_capacity(int device);
-BatchPlan plan_batch(const std::vector<int64_t>& work, const std::vector<int64_t>& max_wg,
-                     int capacity, const PlanModel& model);
+BatchPlan plan_batch(const std::vector<int64_t>& tiles, int cus, const PlanModel& model);
 ising_status batch_sweeps(ising_lattice* const* hs, int32_t count, int64_t n,
-                          int64_t* const* dev_EM, const BatchOptions& opt);
+                          int64_t* const* dev_EM, const BatchOptions& opt, int* form_out);
 
 }  // namespace ising

@@ -275,6 +275,122 @@ __device__ __forceinline__ int64_t wrap_row(int64_t y, int64_t L) {
   return y < 0 ? y + L : (y >= L ? y - L : y);
 }
 
+// Lane-to-word and lane-to-staging maps of one lattice's tile shape.
+struct TileLane {
+  bool wide;
+  int TR, SW, SR;    // rows per tile, staged row width, staged rows
+  int r_off, w_l;    // position of this lane inside a row group
+  bool lane_ok;
+  int st_r, st_c, P; // staging: row/column of this lane within a pass of P rows
+};
+
+template <int WIDEM>
+__device__ __forceinline__ TileLane tile_lane(const TileArgs& a) {
+  TileLane t;
+  // WIDEM: 0 / 1 fixes the row-group shape at compile time, 2 reads it from
+  // the arguments (W >= 64).
+  const bool WIDE = WIDEM == 2 ? (a.g.W >= 64) : (WIDEM == 1);
+  t.wide = WIDE;
+  const int lane = threadIdx.x & 63;
+  const int TW = a.TW, R = a.R;
+  t.TR = 4 * R * a.RPW;
+  t.SW = TW + 2;
+  t.SR = t.TR + 2;
+  if (WIDE) {
+    t.r_off = 0;
+    t.w_l = lane;
+    t.lane_ok = true;
+    // a wave pass loads one staged row of 66 words (lanes 0 and 1 also
+    // load words 64 and 65)
+    t.P = 1;
+    t.st_r = 0;
+    t.st_c = lane;
+  } else {
+    t.r_off = lane / TW;
+    t.w_l = lane - t.r_off * TW;
+    t.lane_ok = t.r_off < R;
+    t.P = 64 / t.SW;
+    t.st_r = lane / t.SW;
+    t.st_c = lane - t.st_r * t.SW;
+    if (t.st_r >= t.P) t.st_r = -1;
+  }
+  return t;
+}
+
+// One tile of one colour step: stage the other colour's rows in LDS, then
+// update this tile's words (RPW row groups per wave).  `colour` and `em`
+// are uniform.  Contains two block barriers.
+template <bool FULL, int WIDEM, bool BUMP_SALU = false>
+__device__ __forceinline__ void process_tile(const TileArgs& a, const TileLane& tl, int colour,
+                                             bool em, int64_t tidx, uint64_t* tile,
+                                             uint32_t& anti, uint32_t& up) {
+  const Geom& g = a.g;
+  const bool WIDE = WIDEM == 2 ? tl.wide : (WIDEM == 1);
+  uint64_t* __restrict__ self = a.planes + (colour ? a.plane_words : 0);
+  const uint64_t* __restrict__ other = a.planes + (colour ? 0 : a.plane_words);
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int R = a.R, RPW = a.RPW, TR = tl.TR, SW = tl.SW, SR = tl.SR;
+  const int r_off = tl.r_off, w_l = tl.w_l, st_r = tl.st_r, st_c = tl.st_c, P = tl.P;
+  const bool lane_ok = tl.lane_ok;
+  const uint32_t ctr3 = a.sid4 | (uint32_t)colour;
+  const int64_t y0 = (tidx / a.segs) * TR;
+  const int32_t w0 = WIDE ? (int32_t)(tidx % a.segs) * 64 : 0;
+  for (int rr0 = wave * P; rr0 < SR; rr0 += 4 * P) {
+    const int rr = rr0 + st_r;
+    if (st_r >= 0 && rr < SR) {
+      // a tile may span more than L rows when L is small: full modulo
+      int64_t yy = (y0 - 1 + rr) % g.L;
+      yy = yy < 0 ? yy + g.L : yy;
+      const int32_t ww = (int32_t)wrap_row(w0 - 1 + st_c, g.W);
+      tile[rr * SW + st_c] = other[yy * g.W + ww];
+      if (WIDE && lane < 2) {
+        const int32_t w2 = (int32_t)wrap_row(w0 + 63 + lane, g.W);
+        tile[rr * SW + 64 + lane] = other[yy * g.W + w2];
+      }
+    }
+  }
+  __syncthreads();
+  for (int j = 0; j < RPW; ++j) {
+    const int r_l = (wave * RPW + j) * R + r_off;
+    const int64_t y = y0 + r_l;
+    const int32_t w = w0 + w_l;
+    if (!(lane_ok && y < g.L && w < g.W)) continue;
+    const uint64_t s = self[y * g.W + w];
+    const int base = (r_l + 1) * SW + (w_l + 1);
+    Nbr n;
+    n.n0 = tile[base];
+    n.n2 = tile[base - SW];
+    n.n3 = tile[base + SW];
+    if (((y + colour) & 1) == 0) {
+      const uint64_t left = tile[base - 1];
+      n.n1 = (n.n0 << 1) | ((w > 0) ? (left >> 63) : ((left >> (g.nb_last - 1)) & 1ull));
+    } else {
+      const uint64_t right = tile[base + 1];
+      n.n1 = (w < g.W - 1) ? ((n.n0 >> 1) | (right << 63))
+                           : ((n.n0 >> 1) | ((right & 1ull) << (g.nb_last - 1)));
+    }
+    uint32_t lo, hi;
+    if (a.hi_mode == 0) {
+      lo = (uint32_t)y * (uint32_t)g.L8 + 16u * (uint32_t)w;
+      hi = 0;
+    } else {
+      const uint64_t gy =
+          (uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)y) * (uint64_t)g.L8;
+      hi = (uint32_t)(gy >> 32);
+      lo = (uint32_t)gy + 16u * (uint32_t)w;
+    }
+    const int nq = (FULL || w < g.W - 1) ? 16 : (g.nb_last >> 2);
+    uint64_t r4, r8;
+    masks_shift<FULL, BUMP_SALU>(lo, hi, nq, a.k0, a.k1, a.t, ctr3, a.t4, a.t8, r4, r8);
+    const uint64_t valid = (FULL || w < g.W - 1) ? ~0ull : low_mask(g.nb_last);
+    const uint64_t s_new = s ^ (flip_mask(s, n, r4, r8) & valid);
+    self[y * g.W + w] = s_new;
+    if (colour == 1 && em) count_word(s_new, n, valid, anti, up);
+  }
+  __syncthreads();
+}
+
 // One colour step of one lattice over the tiles first, first + stride, ...
 // of the tiled layout described above.  `colour` and `em` are uniform; the
 // callers pass constants where they can.  Ends with a block barrier.
@@ -282,101 +398,9 @@ template <bool FULL, int WIDEM, bool BUMP_SALU = false>
 __device__ __forceinline__ void sweep_tiles(const TileArgs& a, int colour, bool em,
                                             int64_t first, int64_t stride, uint64_t* tile,
                                             uint32_t& anti, uint32_t& up) {
-  const Geom& g = a.g;
-  // WIDEM: 0 / 1 fixes the row-group shape at compile time, 2 reads it from
-  // the arguments (W >= 64).
-  const bool WIDE = WIDEM == 2 ? (g.W >= 64) : (WIDEM == 1);
-  uint64_t* __restrict__ self = a.planes + (colour ? a.plane_words : 0);
-  const uint64_t* __restrict__ other = a.planes + (colour ? 0 : a.plane_words);
-  const int lane = threadIdx.x & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int TW = a.TW, R = a.R, RPW = a.RPW;
-  const int TR = 4 * R * RPW;  // rows per tile
-  const int SW = TW + 2;       // staged row width
-  const int SR = TR + 2;       // staged rows
-  // position of this lane inside a row group
-  int r_off, w_l;
-  bool lane_ok;
-  if (WIDE) {
-    r_off = 0;
-    w_l = lane;
-    lane_ok = true;
-  } else {
-    r_off = lane / TW;
-    w_l = lane - r_off * TW;
-    lane_ok = r_off < R;
-  }
-  // staging map: a wave pass loads P staged rows (WIDE: one row of 66 words,
-  // lanes 0 and 1 also load words 64 and 65)
-  int st_r, st_c, P;
-  if (WIDE) {
-    P = 1;
-    st_r = 0;
-    st_c = lane;
-  } else {
-    P = 64 / SW;
-    st_r = lane / SW;
-    st_c = lane - st_r * SW;
-    if (st_r >= P) st_r = -1;
-  }
-  const uint32_t ctr3 = a.sid4 | (uint32_t)colour;
-  for (int64_t tidx = first; tidx < a.tiles; tidx += stride) {
-    const int64_t y0 = (tidx / a.segs) * TR;
-    const int32_t w0 = WIDE ? (int32_t)(tidx % a.segs) * 64 : 0;
-    for (int rr0 = wave * P; rr0 < SR; rr0 += 4 * P) {
-      const int rr = rr0 + st_r;
-      if (st_r >= 0 && rr < SR) {
-        // a tile may span more than L rows when L is small: full modulo
-        int64_t yy = (y0 - 1 + rr) % g.L;
-        yy = yy < 0 ? yy + g.L : yy;
-        const int32_t ww = (int32_t)wrap_row(w0 - 1 + st_c, g.W);
-        tile[rr * SW + st_c] = other[yy * g.W + ww];
-        if (WIDE && lane < 2) {
-          const int32_t w2 = (int32_t)wrap_row(w0 + 63 + lane, g.W);
-          tile[rr * SW + 64 + lane] = other[yy * g.W + w2];
-        }
-      }
-    }
-    __syncthreads();
-    for (int j = 0; j < RPW; ++j) {
-      const int r_l = (wave * RPW + j) * R + r_off;
-      const int64_t y = y0 + r_l;
-      const int32_t w = w0 + w_l;
-      if (!(lane_ok && y < g.L && w < g.W)) continue;
-      const uint64_t s = self[y * g.W + w];
-      const int base = (r_l + 1) * SW + (w_l + 1);
-      Nbr n;
-      n.n0 = tile[base];
-      n.n2 = tile[base - SW];
-      n.n3 = tile[base + SW];
-      if (((y + colour) & 1) == 0) {
-        const uint64_t left = tile[base - 1];
-        n.n1 = (n.n0 << 1) | ((w > 0) ? (left >> 63) : ((left >> (g.nb_last - 1)) & 1ull));
-      } else {
-        const uint64_t right = tile[base + 1];
-        n.n1 = (w < g.W - 1) ? ((n.n0 >> 1) | (right << 63))
-                             : ((n.n0 >> 1) | ((right & 1ull) << (g.nb_last - 1)));
-      }
-      uint32_t lo, hi;
-      if (a.hi_mode == 0) {
-        lo = (uint32_t)y * (uint32_t)g.L8 + 16u * (uint32_t)w;
-        hi = 0;
-      } else {
-        const uint64_t gy =
-            (uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)y) * (uint64_t)g.L8;
-        hi = (uint32_t)(gy >> 32);
-        lo = (uint32_t)gy + 16u * (uint32_t)w;
-      }
-      const int nq = (FULL || w < g.W - 1) ? 16 : (g.nb_last >> 2);
-      uint64_t r4, r8;
-      masks_shift<FULL, BUMP_SALU>(lo, hi, nq, a.k0, a.k1, a.t, ctr3, a.t4, a.t8, r4, r8);
-      const uint64_t valid = (FULL || w < g.W - 1) ? ~0ull : low_mask(g.nb_last);
-      const uint64_t s_new = s ^ (flip_mask(s, n, r4, r8) & valid);
-      self[y * g.W + w] = s_new;
-      if (colour == 1 && em) count_word(s_new, n, valid, anti, up);
-    }
-    __syncthreads();
-  }
+  const TileLane tl = tile_lane<WIDEM>(a);
+  for (int64_t tidx = first; tidx < a.tiles; tidx += stride)
+    process_tile<FULL, WIDEM, BUMP_SALU>(a, tl, colour, em, tidx, tile, anti, up);
 }
 
 template <int C, bool EM, bool FULL, bool WIDE>
@@ -408,79 +432,111 @@ __global__ __launch_bounds__(256) void k_finalize_em(const uint64_t* part, int n
 }
 
 // ---------------------------------------------------------------------
-// Batched persistent kernel (many lattices of uneven size and temperature
-// in one launch).  Each workgroup walks its item list; for every item it
-// runs all n sweeps of its share of that lattice.  Between colour steps the
-// nwg workgroups of a lattice meet at an atomic counter (agent-scope
-// release/acquire, so the other colour's words written on any XCD are
-// visible); a lattice with one workgroup only needs the block barrier.
-// Waits are bounded by a wall-clock limit: on expiry the workgroup records
-// the failure in *err and leaves, so the grid always drains.
+// Batched sweeps over many lattices of uneven size and temperature.
+//
+// k_fused<C>: one launch advances colour C of every lattice of the batch by
+// one sweep.  The tiles of all lattices form one flat list that the grid
+// walks with a stride, so the work of a colour step is balanced over the
+// whole GPU whatever the mix of sizes; the kernel boundary is the barrier
+// between colour steps (a device-wide barrier inside a kernel would need
+// an agent-scope release/acquire of the XCD L2s at every colour step).
+// The sweep index is read from device memory (*kbase + klocal) so that a
+// captured chunk of K sweeps can be replayed from a hipGraph, followed by
+// k_advance (*kbase += K).  Colour 1 writes each tile's (anti-aligned
+// bond, up spin) counts to part[(k & 1)][tile]; colour 0 of the next sweep
+// (or k_fused_finalize after the last one) reduces them per lattice into
+// (E, M) = (2A - 2N, 2P - N).
+//
+// k_batch: a persistent kernel for batches of small lattices that each fit
+// one workgroup: every workgroup runs its packed list of lattices for all
+// n sweeps with block barriers only (one launch in total).
 // ---------------------------------------------------------------------
-__device__ __forceinline__ bool lattice_barrier(uint32_t* bar, uint32_t target, uint32_t* err,
-                                                uint64_t limit, int* flag) {
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    const uint64_t start = __builtin_amdgcn_s_memrealtime();
-    int ok = 1;
-    while (__hip_atomic_load(bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
-      __builtin_amdgcn_s_sleep(2);
-      if (__builtin_amdgcn_s_memrealtime() - start > limit) {
-        __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        ok = 0;
-        break;
-      }
+__device__ __forceinline__ void finalize_tiles(const FusedArgs& f, uint32_t k, uint32_t* red) {
+  const uint32_t* part = f.part + (size_t)(k & 1u) * 2 * f.ntiles;
+  for (int l = blockIdx.x; l < f.nlat; l += gridDim.x) {
+    const FusedLattice Lt = ((const FusedLattice ISING_CONSTANT_AS*)f.lat)[l];
+    if (Lt.EM == nullptr) continue;
+    uint32_t a = 0, p = 0;
+    for (int64_t i = threadIdx.x; i < Lt.ntiles; i += blockDim.x) {
+      a += part[2 * (Lt.first_tile + i)];
+      p += part[2 * (Lt.first_tile + i) + 1];
     }
-    *flag = ok;
+    block_sum2(a, p, red);
+    if (threadIdx.x == 0) {
+      const int64_t L = Lt.ta.g.L;
+      Lt.EM[2 * (int64_t)k] = 2 * (int64_t)a - 2 * L * L;
+      Lt.EM[2 * (int64_t)k + 1] = 2 * (int64_t)p - L * L;
+    }
+    __syncthreads();
   }
-  __syncthreads();
-  __threadfence();
-  return *flag != 0;
 }
 
-__device__ __forceinline__ bool run_lattice(const BatchLattice& Lt, int rank, int64_t n,
-                                            uint32_t* err, uint64_t limit, uint64_t* tile,
-                                            uint32_t* red, uint64_t* red64, int* flag) {
-  TileArgs a = Lt.ta;
-  const uint32_t t0 = Lt.ta.t;
-  const bool em = Lt.EM != nullptr;
-  const int nwg = Lt.nwg;
-  uint32_t arrivals = 0;
-  for (int64_t k = 0; k < n; ++k) {
-    a.t = t0 + (uint32_t)k;
+template <int C>
+__global__ __launch_bounds__(256) void k_fused(FusedArgs f) {
+  __shared__ uint64_t tile[kTileLdsMaxWords];
+  __shared__ uint32_t red[8];
+  const uint32_t k = *((const uint32_t ISING_CONSTANT_AS*)f.kbase) + (uint32_t)f.klocal;
+  if (C == 0 && k > 0) finalize_tiles(f, k - 1, red);
+  const int G = gridDim.x;
+  const int b = blockIdx.x;
+  const int lb = (G % 8 == 0) ? (b % 8) * (G / 8) + b / 8 : b;
+  uint32_t* part = f.part + (size_t)(k & 1u) * 2 * f.ntiles;
+  for (int64_t tidx = lb; tidx < f.ntiles; tidx += G) {
+    const FusedTile ft = ((const FusedTile ISING_CONSTANT_AS*)f.tiles)[tidx];
+    const FusedLattice Lt = ((const FusedLattice ISING_CONSTANT_AS*)f.lat)[ft.lattice];
+    TileArgs a = Lt.ta;
+    a.t = Lt.ta.t + k;
+    const bool em = C == 1 && Lt.EM != nullptr;
+    const TileLane tl = tile_lane<2>(a);
     uint32_t anti = 0, up = 0;
-    sweep_tiles<false, 2, true>(a, 0, false, rank, nwg, tile, anti, up);
-    if (nwg > 1 && !lattice_barrier(Lt.bar, (++arrivals) * (uint32_t)nwg, err, limit, flag))
-      return false;
-    sweep_tiles<false, 2, true>(a, 1, em, rank, nwg, tile, anti, up);
+    process_tile<false, 2, true>(a, tl, C, em, ft.local, tile, anti, up);
     if (em) {
       block_sum2(anti, up, red);
       if (threadIdx.x == 0) {
-        if (nwg == 1) {
-          Lt.EM[2 * k] = 2 * (int64_t)anti - 2 * a.g.L * a.g.L;
-          Lt.EM[2 * k + 1] = 2 * (int64_t)up - a.g.L * a.g.L;
-        } else {
-          Lt.part[2 * rank] = anti;
-          Lt.part[2 * rank + 1] = up;
-        }
+        part[2 * tidx] = anti;
+        part[2 * tidx + 1] = up;
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_fused_finalize(FusedArgs f) {
+  __shared__ uint32_t red[8];
+  const uint32_t k = *((const uint32_t ISING_CONSTANT_AS*)f.kbase) + (uint32_t)f.klocal;
+  finalize_tiles(f, k, red);
+}
+
+__global__ void k_advance(uint32_t* kbase, uint32_t by) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *kbase += by;
+}
+
+__device__ __forceinline__ void run_packed_lattice(const BatchLattice& Lt, int64_t n,
+                                                   uint64_t* tile, uint32_t* red) {
+  TileArgs a = Lt.ta;
+  const uint32_t t0 = Lt.ta.t;
+  const bool em = Lt.EM != nullptr;
+  const TileLane tl = tile_lane<2>(a);
+  for (int64_t k = 0; k < n; ++k) {
+    a.t = t0 + (uint32_t)k;
+    uint32_t anti = 0, up = 0;
+    for (int64_t tidx = 0; tidx < a.tiles; ++tidx)
+      process_tile<false, 2, true>(a, tl, 0, false, tidx, tile, anti, up);
+    for (int64_t tidx = 0; tidx < a.tiles; ++tidx)
+      process_tile<false, 2, true>(a, tl, 1, em, tidx, tile, anti, up);
+    if (em) {
+      block_sum2(anti, up, red);
+      if (threadIdx.x == 0) {
+        Lt.EM[2 * k] = 2 * (int64_t)anti - 2 * a.g.L * a.g.L;
+        Lt.EM[2 * k + 1] = 2 * (int64_t)up - a.g.L * a.g.L;
       }
       __syncthreads();
     }
-    if (nwg > 1) {
-      if (!lattice_barrier(Lt.bar, (++arrivals) * (uint32_t)nwg, err, limit, flag)) return false;
-      if (em && rank == 0) finalize_partials(Lt.part, nwg, a.g.L, Lt.EM + 2 * k, red64);
-    }
   }
-  return true;
 }
 
 __global__ __launch_bounds__(256) void k_batch(BatchArgs b) {
   __shared__ uint64_t tile[kTileLdsMaxWords];
-  __shared__ uint64_t red64[8];
   __shared__ uint32_t red[8];
-  __shared__ int flag;
   // The tables are read-only for the whole launch: read them through the
   // constant address space so that they land in SGPRs (scalar loads).
   typedef const BatchWG ISING_CONSTANT_AS* WgPtr;
@@ -490,9 +546,26 @@ __global__ __launch_bounds__(256) void k_batch(BatchArgs b) {
   for (int it = 0; it < wg.n_items; ++it) {
     const BatchItem item = ((ItemPtr)b.items)[wg.first_item + it];
     const BatchLattice Lt = ((LatPtr)b.lat)[item.lattice];
-    if (!run_lattice(Lt, item.rank, b.n, b.err, b.spin_limit, tile, red, red64, &flag))
-      return;
+    run_packed_lattice(Lt, b.n, tile, red);
   }
+}
+
+hipError_t launch_fused(hipStream_t st, int colour, const FusedArgs& f, int blocks) {
+  if (colour == 0)
+    hipLaunchKernelGGL(k_fused<0>, dim3(blocks), dim3(256), 0, st, f);
+  else
+    hipLaunchKernelGGL(k_fused<1>, dim3(blocks), dim3(256), 0, st, f);
+  return hipGetLastError();
+}
+
+hipError_t launch_fused_finalize(hipStream_t st, const FusedArgs& f, int blocks) {
+  hipLaunchKernelGGL(k_fused_finalize, dim3(blocks), dim3(256), 0, st, f);
+  return hipGetLastError();
+}
+
+hipError_t launch_advance(hipStream_t st, uint32_t* kbase, uint32_t by) {
+  hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, st, kbase, by);
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------
@@ -530,22 +603,9 @@ hipError_t launch_finalize_em(hipStream_t st, const uint64_t* part, int blocks, 
   hipLaunchKernelGGL(k_finalize_em, dim3(1), dim3(256), 0, st, part, blocks, L, EM);
   return hipGetLastError();
 }
-hipError_t launch_batch(hipStream_t st, const BatchArgs& a, int blocks, bool cooperative) {
-  void* args[] = {(void*)&a};
-  const void* fn = (const void*)k_batch;
-  if (!cooperative) {
-    hipLaunchKernelGGL(k_batch, dim3(blocks), dim3(256), 0, st, a);
-    return hipGetLastError();
-  }
-  return hipLaunchCooperativeKernel(fn, dim3(blocks), dim3(256), args, 0, st);
-}
-
-int batch_max_blocks_per_cu() {
-  int n = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void*)k_batch, 256,
-                                                   0) != hipSuccess)
-    return 0;
-  return n;
+hipError_t launch_batch(hipStream_t st, const BatchArgs& a, int blocks) {
+  hipLaunchKernelGGL(k_batch, dim3(blocks), dim3(256), 0, st, a);
+  return hipGetLastError();
 }
 
 hipError_t launch_init(hipStream_t st, uint64_t* planes, const Geom& g, uint32_t k0, uint32_t k1,

@@ -55,18 +55,30 @@ hipError_t launch_tile_sweep(hipStream_t st, int colour, const TileArgs& a, int 
 hipError_t launch_finalize_em(hipStream_t st, const uint64_t* part, int blocks, int64_t L,
                               int64_t* EM);
 
-// Batched persistent kernel: every workgroup runs a list of items; an item
-// is (lattice, rank) and the lattice's tiles rank, rank + nwg, ... are that
-// workgroup's share for all n sweeps.  Lattices with nwg > 1 synchronise
-// their workgroups with an atomic counter after each colour step.
+// Batched sweeps (see ising_kernels.hip).
+struct FusedLattice {
+  TileArgs ta;          // RPW = 1 tiles; ta.t = sweep counter of the call's first sweep
+  int64_t* EM;          // n x 2 per-sweep (E, M), or null
+  int64_t first_tile;   // first entry of this lattice in the flat tile list
+  int64_t ntiles;
+};
+struct FusedTile {
+  int32_t lattice;
+  int32_t local;        // tile index inside the lattice
+};
+struct FusedArgs {
+  const FusedLattice* lat;
+  int32_t nlat;
+  int32_t klocal;       // sweep index inside a replayed chunk
+  const FusedTile* tiles;
+  int64_t ntiles;
+  const uint32_t* kbase;  // device word: sweep index of the chunk's first sweep
+  uint32_t* part;       // 2 slots x ntiles x (anti, up)
+};
+
 struct BatchLattice {
   TileArgs ta;          // tile shape, key, thresholds; ta.t is the first sweep counter
   int64_t* EM;          // n x 2 per-sweep (E, M), or null
-  uint64_t* part;       // nwg x 2 partial counts (nwg > 1 with EM)
-  uint32_t* bar;        // barrier counter, 0 at launch
-  int32_t nwg;          // workgroups sharing this lattice
-  int32_t full, wide;   // tile variant
-  int32_t pad;
 };
 struct BatchItem {
   int32_t lattice;
@@ -81,12 +93,12 @@ struct BatchArgs {
   const BatchItem* items;
   const BatchWG* wgs;
   int64_t n;            // sweeps
-  uint32_t* err;        // set to 1 if a barrier wait exceeds the time limit
-  uint64_t spin_limit;  // s_memrealtime ticks (100 MHz)
 };
 
-hipError_t launch_batch(hipStream_t st, const BatchArgs& a, int blocks, bool cooperative);
-int batch_max_blocks_per_cu();
+hipError_t launch_fused(hipStream_t st, int colour, const FusedArgs& f, int blocks);
+hipError_t launch_fused_finalize(hipStream_t st, const FusedArgs& f, int blocks);
+hipError_t launch_advance(hipStream_t st, uint32_t* kbase, uint32_t by);
+hipError_t launch_batch(hipStream_t st, const BatchArgs& a, int blocks);
 
 hipError_t launch_init(hipStream_t st, uint64_t* planes, const Geom& g, uint32_t k0, uint32_t k1,
                        uint32_t sid4, int init, int blocks);

@@ -12,12 +12,20 @@ Tuning default_tuning(int64_t L) {
   return t;
 }
 
+PlanModel default_model() {
+  PlanModel m;
+  m.wg_per_cu = 8;          // 16.4 KB LDS and <= 64 VGPRs per lane allow 8 per CU
+  m.tile_s_full = 13e-6;    // ~1000 VALU instructions per lane, 8 waves per SIMD
+  m.tile_s_alone = 2.5e-6;  // one wave per SIMD: issue plus memory latency
+  m.launch_gap_s = 4e-6;
+  return m;
+}
+
 BatchOptions default_batch_options() {
   BatchOptions o;
   o.model = default_model();
-  o.max_blocks = 0;
-  o.cooperative = true;
-  o.barrier_timeout_s = 2.0;
+  o.force_form = -1;
+  o.graph_chunk = 32;
   return o;
 }
 

@@ -84,6 +84,8 @@ def lib():
         "ising_set_sweep": ([vp, u64], i32),
         "ising_get_info": ([vp, P(i64), P(i64), P(vp)], i32),
         "ising_multi_sweep": ([P(vp), i32, i64, P(vp)], i32),
+        "ising_multi_sweep_form": ([P(vp), i32, i64, P(vp), i32, i32], i32),
+        "ising_batch_plan": ([P(i64), i32, i32, P(i32), P(i32), P(ctypes.c_double)], i32),
         "ising_server_create": ([vp, ctypes.c_size_t, vp, i32, P(vp)], i32),
         "ising_batch_submit": ([vp, P(ising_request), i32, P(u64)], i32),
         "ising_server_step": ([vp], i32),
@@ -221,11 +223,23 @@ class Lattice:
         return int(L.value), int(W.value), int(p.value or 0)
 
 
-def multi_sweep(lattices: Sequence[Lattice], n: int, EMs=None):
-    """n sweeps on every lattice in one fused launch (same device and stream)."""
-    arr = (ctypes.c_void_p * len(lattices))(*[lat.h.value for lat in lattices])
+def batch_plan(Ls: Sequence[int], cus: int = 256):
+    """(form, grid size, model seconds per sweep) the batched path would use."""
+    n = len(Ls)
+    arr = (ctypes.c_int64 * max(n, 1))(*[int(L) for L in Ls])
+    form, blocks, est = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+    check(lib().ising_batch_plan(arr, n, int(cus), ctypes.byref(form), ctypes.byref(blocks),
+                                 ctypes.byref(est)))
+    return ("packed" if form.value == 1 else "fused"), int(blocks.value), float(est.value)
+
+
+def multi_sweep(lattices: Sequence[Lattice], n: int, EMs=None, form=None, graph_chunk=-1):
+    """n sweeps on every lattice together (same device and stream).
+    form: None (cost model), "fused" or "packed"."""
+    arr = (ctypes.c_void_p * max(len(lattices), 1))(*[lat.h.value for lat in lattices])
     em_arr = None
     if EMs is not None:
-        em_arr = (ctypes.c_void_p * len(lattices))(
+        em_arr = (ctypes.c_void_p * max(len(lattices), 1))(
             *[(e.data_ptr() if e is not None else None) for e in EMs])
-    check(lib().ising_multi_sweep(arr, len(lattices), int(n), em_arr))
+    f = {None: -1, "fused": 0, "packed": 1}[form]
+    check(lib().ising_multi_sweep_form(arr, len(lattices), int(n), em_arr, f, int(graph_chunk)))

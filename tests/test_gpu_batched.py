@@ -40,14 +40,15 @@ def _make(I, specs):
     return lats
 
 
-def _batched_vs_plain(I, specs, n, chunks=1):
+def _batched_vs_plain(I, specs, n, chunks=1, form=None, graph_chunk=-1):
     import torch
     batch = _make(I, specs)
     plain = _make(I, specs)
     EMb = [torch.empty((n, 2), dtype=torch.int64, device="cuda") for _ in specs]
     per = n // chunks
     for c in range(chunks):
-        I.multi_sweep(batch, per, [e[c * per:(c + 1) * per] for e in EMb])
+        I.multi_sweep(batch, per, [e[c * per:(c + 1) * per] for e in EMb], form=form,
+                      graph_chunk=graph_chunk)
     torch.cuda.synchronize()
     for i, (lat_b, lat_p) in enumerate(zip(batch, plain)):
         EMp = lat_p.sweep_em(n).cpu().numpy()
@@ -59,27 +60,32 @@ def _batched_vs_plain(I, specs, n, chunks=1):
     return batch
 
 
-def test_mixed_sizes_match_plain(I):
-    H = workloads.INIT_HOT
-    specs = [(64, 2.2, 1, 0, H), (128, 2.25, 1, 1, H), (256, 2.3, 2, 2, H), (512, 2.27, 3, 3, H),
-             (1024, 2.269, 1, 4, H), (96, 3.0, 5, 5, H), (160, 1.8, 6, 6, workloads.INIT_COLD_UP),
-             (130, 2.4, 7, 7, H), (6, 2.0, 8, 8, H), (2048, 2.3, 9, 9, H)]
-    _say("case mixed sizes", [s[0] for s in specs])
-    _batched_vs_plain(I, specs, 24, chunks=2)
+MIXED = [(64, 2.2, 1, 0, 2), (128, 2.25, 1, 1, 2), (256, 2.3, 2, 2, 2), (512, 2.27, 3, 3, 2),
+         (1024, 2.269, 1, 4, 2), (96, 3.0, 5, 5, 2), (160, 1.8, 6, 6, 0), (130, 2.4, 7, 7, 2),
+         (6, 2.0, 8, 8, 2), (2048, 2.3, 9, 9, 2)]
 
 
-def test_single_large_lattice_many_workgroups(I):
+@pytest.mark.parametrize("form,graph_chunk", [(None, -1), ("fused", 0), ("fused", 4),
+                                              ("packed", -1)])
+def test_mixed_sizes_match_plain(I, form, graph_chunk):
+    _say("case mixed sizes form=%s chunk=%d" % (form, graph_chunk))
+    _batched_vs_plain(I, MIXED, 24, chunks=2, form=form, graph_chunk=graph_chunk)
+
+
+@pytest.mark.parametrize("form", ["fused", "packed"])
+def test_single_large_lattice(I, form):
     specs = [(4096, 2.269185, 11, 3, workloads.INIT_HOT)]
-    _say("case single 4096")
-    _batched_vs_plain(I, specs, 12)
+    _say("case single 4096 form=%s" % form)
+    _batched_vs_plain(I, specs, 12 if form == "fused" else 3, form=form)
 
 
-def test_wide_rows_and_partial_words(I):
+@pytest.mark.parametrize("form", ["fused", "packed"])
+def test_wide_rows_and_partial_words(I, form):
     H = workloads.INIT_HOT
     specs = [(8192, 2.1, 1, 1, H), (8224, 2.5, 2, 2, H), (1000, 2.269, 3, 3, H),
              (520, 2.3, 4, 4, H), (40, 2.0, 5, 5, H)]
-    _say("case wide and partial", [s[0] for s in specs])
-    _batched_vs_plain(I, specs, 6)
+    _say("case wide and partial form=%s" % form)
+    _batched_vs_plain(I, specs, 6 if form == "fused" else 2, form=form)
 
 
 def test_small_members_match_oracle(I):
@@ -100,7 +106,7 @@ def test_fss_grid_subset_matches_plain(I):
     grid = workloads.fss_grid(sizes=[64, 128, 256, 512], temps=workloads.FSS_TEMPS[::8])
     specs = [(g.L, g.T, g.seed, g.stream_id, g.init) for g in grid]
     _say("case fss subset", len(specs))
-    _batched_vs_plain(I, specs, 40)
+    _batched_vs_plain(I, specs, 70, form="fused", graph_chunk=8)
 
 
 def test_batched_errors(I):
