@@ -111,7 +111,7 @@ BatchPlan plan_batch(const std::vector<int64_t>& tiles, int cus, const PlanModel
 }
 
 static ising_status run_fused(ising_lattice* const* hs, const std::vector<int>& idx,
-                              const std::vector<TileArgs>& targs, int64_t n,
+                              const std::vector<TileArgs>& targs, int64_t n, const int64_t* nsw,
                               int64_t* const* dev_EM, const BatchOptions& opt, DeviceTable& T,
                               int blocks) {
   hipStream_t stream = hs[idx[0]]->stream;
@@ -129,6 +129,7 @@ static ising_status run_fused(ising_lattice* const* hs, const std::vector<int>& 
     any_em = any_em || F.EM != nullptr;
     F.first_tile = (int64_t)tiles.size();
     F.ntiles = F.ta.tiles;
+    F.nsweeps = nsw ? nsw[i] : n;
     for (int64_t t = 0; t < F.ntiles; ++t) tiles.push_back(FusedTile{j, (int32_t)t});
   }
   const int64_t ntiles = (int64_t)tiles.size();
@@ -206,7 +207,7 @@ static ising_status run_fused(ising_lattice* const* hs, const std::vector<int>& 
 }
 
 static ising_status run_packed(ising_lattice* const* hs, const std::vector<int>& idx,
-                               const std::vector<TileArgs>& targs, int64_t n,
+                               const std::vector<TileArgs>& targs, int64_t n, const int64_t* nsw,
                                int64_t* const* dev_EM, const BatchPlan& plan, DeviceTable& T) {
   hipStream_t stream = hs[idx[0]]->stream;
   const int nl = (int)idx.size();
@@ -217,6 +218,7 @@ static ising_status run_packed(ising_lattice* const* hs, const std::vector<int>&
     lat[j].ta = targs[i];
     lat[j].ta.t = (uint32_t)hs[i]->sweep;
     lat[j].EM = dev_EM ? dev_EM[i] : nullptr;
+    lat[j].nsweeps = nsw ? nsw[i] : n;
   }
   std::vector<BatchWG> wgs(plan.packs.size());
   std::vector<BatchItem> items;
@@ -250,7 +252,8 @@ static ising_status run_packed(ising_lattice* const* hs, const std::vector<int>&
 }
 
 ising_status batch_sweeps(ising_lattice* const* hs, int32_t count, int64_t n,
-                          int64_t* const* dev_EM, const BatchOptions& opt, int* form_out) {
+                          const int64_t* nsw, int64_t* const* dev_EM, const BatchOptions& opt,
+                          int* form_out) {
   if (form_out) *form_out = -1;
   if (count == 0 || n == 0) return ISING_OK;
   const int device = hs[0]->device;
@@ -259,8 +262,15 @@ ising_status batch_sweeps(ising_lattice* const* hs, int32_t count, int64_t n,
   for (int i = 0; i < count; ++i) {
     TileArgs ta;
     if (tile_args(hs[i], &ta)) {
-      ta.RPW = 1;  // finest tiles balance best across the flat list
-      const int64_t TR = 4 * (int64_t)ta.R;
+      // fine tiles balance best across the flat list; lattices with many
+      // tiles take two row groups per wave (less staging per word)
+      ta.RPW = 1;
+      int64_t TR = 4 * (int64_t)ta.R;
+      if (((hs[i]->L + TR - 1) / TR) * ta.segs >= 256 &&
+          (2 * TR + 2) * (ta.TW + 2) <= kTileLdsMaxWords) {
+        ta.RPW = 2;
+        TR *= 2;
+      }
       ta.tiles = ((hs[i]->L + TR - 1) / TR) * ta.segs;
       targs[i] = ta;
       tiled.push_back(i);
@@ -269,23 +279,32 @@ ising_status batch_sweeps(ising_lattice* const* hs, int32_t count, int64_t n,
     }
   }
   for (int i : other) {
-    ising_status st = enqueue_sweeps(hs[i], n, dev_EM ? dev_EM[i] : nullptr);
+    // the plain path reads the handle's counter: advance a copy of it
+    ising_lattice tmp = *hs[i];
+    ising_status st = enqueue_sweeps(&tmp, nsw ? nsw[i] : n, dev_EM ? dev_EM[i] : nullptr);
     if (st != ISING_OK) return st;
   }
-  if (tiled.empty()) return ISING_OK;
+  if (tiled.empty()) {
+    hipError_t e = hipStreamSynchronize(hs[0]->stream);
+    return e == hipSuccess ? ISING_OK : hip_fail(e, "batched sweeps: synchronize");
+  }
   DeviceTable& T = table_for(device);
   std::lock_guard<std::mutex> lock(T.m);
   const int cus = cu_count(T, device);
   if (cus <= 0) return fail(ISING_EDEVICE, "batched sweeps: no device properties");
   std::vector<int64_t> tiles;
-  for (int i : tiled) tiles.push_back(targs[i].tiles);
+  for (int i : tiled) tiles.push_back(tile_cost(targs[i].tiles, targs[i].RPW));
   const BatchPlan plan = plan_batch(tiles, cus, opt.model);
   bool packed = plan.packed;
   if (opt.force_form == 0) packed = false;
   if (opt.force_form == 1) packed = true;
   if (form_out) *form_out = packed ? 1 : 0;
-  if (packed) return run_packed(hs, tiled, targs, n, dev_EM, plan, T);
-  return run_fused(hs, tiled, targs, n, dev_EM, opt, T, plan.fused_blocks);
+  if (packed) return run_packed(hs, tiled, targs, n, nsw, dev_EM, plan, T);
+  // the fused grid walks actual tiles; size it for them
+  int64_t ntiles = 0;
+  for (int i : tiled) ntiles += targs[i].tiles;
+  const int blocks = (int)std::min<int64_t>(std::max<int64_t>(ntiles, 1), plan.fused_blocks);
+  return run_fused(hs, tiled, targs, n, nsw, dev_EM, opt, T, blocks);
 }
 
 }  // namespace ising
@@ -346,7 +365,7 @@ extern "C" ising_status ising_multi_sweep_form(ising_t* const* hs, int32_t count
   BatchOptions opt = default_batch_options();
   opt.force_form = form;
   if (graph_chunk >= 0) opt.graph_chunk = graph_chunk;
-  st = batch_sweeps(hs, count, n, dev_EM, opt, nullptr);
+  st = batch_sweeps(hs, count, n, nullptr, dev_EM, opt, nullptr);
   if (st != ISING_OK) return st;
   for (int32_t i = 0; i < count; ++i) hs[i]->sweep += (uint64_t)n;
   return ISING_OK;

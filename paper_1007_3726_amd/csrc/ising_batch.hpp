@@ -17,6 +17,9 @@ struct PlanModel {
   double launch_gap_s;  // gap between dependent launches
 };
 
+// tile-steps (one word per lane) a lattice with these tile arguments costs per colour
+inline int64_t tile_cost(int64_t tiles, int32_t rpw) { return tiles * (int64_t)rpw; }
+
 struct BatchPlan {
   int fused_blocks = 0;                 // grid of the fused launches
   double fused_s = 0.0;                 // model: seconds per sweep, fused form
@@ -34,7 +37,10 @@ struct BatchOptions {
 PlanModel default_model();
 BatchOptions default_batch_options();
 BatchPlan plan_batch(const std::vector<int64_t>& tiles, int cus, const PlanModel& model);
+// Advance hs[i] by nsw[i] sweeps (nsw may be null: n for all), n = max nsw.
+// Does not change the handles' sweep counters.
 ising_status batch_sweeps(ising_lattice* const* hs, int32_t count, int64_t n,
-                          int64_t* const* dev_EM, const BatchOptions& opt, int* form_out);
+                          const int64_t* nsw, int64_t* const* dev_EM, const BatchOptions& opt,
+                          int* form_out);
 
 }  // namespace ising

@@ -455,7 +455,7 @@ __device__ __forceinline__ void finalize_tiles(const FusedArgs& f, uint32_t k, u
   const uint32_t* part = f.part + (size_t)(k & 1u) * 2 * f.ntiles;
   for (int l = blockIdx.x; l < f.nlat; l += gridDim.x) {
     const FusedLattice Lt = ((const FusedLattice ISING_CONSTANT_AS*)f.lat)[l];
-    if (Lt.EM == nullptr) continue;
+    if (Lt.EM == nullptr || (int64_t)k >= Lt.nsweeps) continue;
     uint32_t a = 0, p = 0;
     for (int64_t i = threadIdx.x; i < Lt.ntiles; i += blockDim.x) {
       a += part[2 * (Lt.first_tile + i)];
@@ -484,12 +484,16 @@ __global__ __launch_bounds__(256) void k_fused(FusedArgs f) {
   for (int64_t tidx = lb; tidx < f.ntiles; tidx += G) {
     const FusedTile ft = ((const FusedTile ISING_CONSTANT_AS*)f.tiles)[tidx];
     const FusedLattice Lt = ((const FusedLattice ISING_CONSTANT_AS*)f.lat)[ft.lattice];
+    if ((int64_t)k >= Lt.nsweeps) continue;  // this lattice has finished its sweeps
     TileArgs a = Lt.ta;
     a.t = Lt.ta.t + k;
     const bool em = C == 1 && Lt.EM != nullptr;
     const TileLane tl = tile_lane<2>(a);
     uint32_t anti = 0, up = 0;
-    process_tile<false, 2, true>(a, tl, C, em, ft.local, tile, anti, up);
+    if (a.g.nb_last == 64)
+      process_tile<true, 2, true>(a, tl, C, em, ft.local, tile, anti, up);
+    else
+      process_tile<false, 2, true>(a, tl, C, em, ft.local, tile, anti, up);
     if (em) {
       block_sum2(anti, up, red);
       if (threadIdx.x == 0) {
@@ -516,7 +520,8 @@ __device__ __forceinline__ void run_packed_lattice(const BatchLattice& Lt, int64
   const uint32_t t0 = Lt.ta.t;
   const bool em = Lt.EM != nullptr;
   const TileLane tl = tile_lane<2>(a);
-  for (int64_t k = 0; k < n; ++k) {
+  const int64_t nk = Lt.nsweeps < n ? Lt.nsweeps : n;
+  for (int64_t k = 0; k < nk; ++k) {
     a.t = t0 + (uint32_t)k;
     uint32_t anti = 0, up = 0;
     for (int64_t tidx = 0; tidx < a.tiles; ++tidx)

@@ -57,10 +57,12 @@ hipError_t launch_finalize_em(hipStream_t st, const uint64_t* part, int blocks, 
 
 // Batched sweeps (see ising_kernels.hip).
 struct FusedLattice {
-  TileArgs ta;          // RPW = 1 tiles; ta.t = sweep counter of the call's first sweep
-  int64_t* EM;          // n x 2 per-sweep (E, M), or null
+  TileArgs ta;          // tile shape; ta.t = sweep counter of the call's first sweep
+  int64_t* EM;          // nsweeps x 2 per-sweep (E, M), or null
   int64_t first_tile;   // first entry of this lattice in the flat tile list
   int64_t ntiles;
+  int64_t nsweeps;      // sweeps this lattice takes in the call (<= the call's n)
+  int64_t rpw_cost;     // unused by the kernels (host bookkeeping)
 };
 struct FusedTile {
   int32_t lattice;
@@ -78,7 +80,8 @@ struct FusedArgs {
 
 struct BatchLattice {
   TileArgs ta;          // tile shape, key, thresholds; ta.t is the first sweep counter
-  int64_t* EM;          // n x 2 per-sweep (E, M), or null
+  int64_t* EM;          // nsweeps x 2 per-sweep (E, M), or null
+  int64_t nsweeps;      // sweeps this lattice takes in the launch
 };
 struct BatchItem {
   int32_t lattice;

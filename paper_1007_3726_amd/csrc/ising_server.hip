@@ -1,28 +1,378 @@
-// Served mode (continuous batching).  Not built yet: every entry point
-// reports EINVAL.
+// Served mode: continuous batching of independent Ising simulations.
+//
+// A server owns a device arena given by the caller (the HBM budget) and a
+// FIFO of submitted requests.  Each ising_server_step is one quantum:
+//   1. admission: queued requests are admitted in submission order while
+//      their lattice and per-sweep (E, M) series fit in the free arena
+//      (first-fit allocator, 256-byte aligned); a request larger than the
+//      whole arena is rejected at submission;
+//   2. one batched call advances every active lattice by up to
+//      quantum_sweeps sweeps (fewer for a request that has fewer left), all
+//      lattices together in fused launches or one packed launch;
+//   3. retirement: finished requests copy their series/spins to the
+//      caller's host buffers, get exact moment sums, a completion time, and
+//      free their arena space, so the next step can admit more.
+// A request's result is a pure function of its own parameters: its
+// uniforms are keyed by (seed, stream_id, sweep), never by arena slot or
+// by the mix it ran in.
+//
+// Fault injection (tests): a quantum armed with ising_server_inject_fault
+// snapshots the active lattices to host memory, runs, is declared failed,
+// restores the snapshot and runs again; the final results are unchanged.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <set>
+#include <vector>
+
+#include "ising_batch.hpp"
 #include "ising_runtime.hpp"
+
+namespace ising {
+namespace {
+
+double now_s() {
+  using clock = std::chrono::steady_clock;
+  return std::chrono::duration<double>(clock::now().time_since_epoch()).count();
+}
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// First-fit allocator over [0, size) with coalescing free list.
+class Arena {
+ public:
+  explicit Arena(size_t size) { free_[0] = size; }
+  bool alloc(size_t bytes, size_t* off) {
+    bytes = align256(bytes);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= bytes) {
+        *off = it->first;
+        const size_t rest = it->second - bytes;
+        const size_t at = it->first + bytes;
+        free_.erase(it);
+        if (rest) free_[at] = rest;
+        used_ += bytes;
+        return true;
+      }
+    }
+    return false;
+  }
+  void release(size_t off, size_t bytes) {
+    bytes = align256(bytes);
+    used_ -= bytes;
+    auto it = free_.emplace(off, bytes).first;
+    auto next = std::next(it);
+    if (next != free_.end() && it->first + it->second == next->first) {
+      it->second += next->second;
+      free_.erase(next);
+    }
+    if (it != free_.begin()) {
+      auto prev = std::prev(it);
+      if (prev->first + prev->second == it->first) {
+        prev->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+  size_t used() const { return used_; }
+
+ private:
+  std::map<size_t, size_t> free_;
+  size_t used_ = 0;
+};
+
+enum class State { Queued, Active, Done };
+
+struct Job {
+  uint64_t ticket;
+  ising_request req;
+  State state = State::Queued;
+  size_t off = 0, bytes = 0;   // arena slice: lattice then series
+  ising_lattice* h = nullptr;
+  int64_t* dev_series = nullptr;
+  int64_t done = 0;            // sweeps completed
+  ising_result res;
+};
+
+size_t job_bytes(const ising_request& r) {
+  return align256(lattice_bytes(r.L)) + align256((size_t)r.n_sweeps * 2 * sizeof(int64_t));
+}
+
+}  // namespace
+}  // namespace ising
 
 using namespace ising;
 
+struct ising_server {
+  char* arena_base;
+  size_t arena_bytes;
+  hipStream_t stream;
+  int32_t quantum;
+  Arena arena;
+  uint64_t next_ticket = 1;
+  std::map<uint64_t, Job> jobs;
+  std::deque<uint64_t> queue;
+  std::vector<uint64_t> active;
+  std::set<int64_t> faults;
+  int64_t quanta = 0, admitted = 0, finished = 0, peak = 0, recovered = 0;
+  explicit ising_server(size_t bytes) : arena(bytes) {}
+};
+
+namespace ising {
+namespace {
+
+ising_status admit(ising_server* s) {
+  while (!s->queue.empty()) {
+    Job& j = s->jobs.at(s->queue.front());
+    size_t off;
+    if (!s->arena.alloc(j.bytes, &off)) break;  // strict FIFO: wait for space
+    j.off = off;
+    ising_t* h = nullptr;
+    const size_t lb = align256(lattice_bytes(j.req.L));
+    ising_status st = ising_create(j.req.L, j.req.seed, j.req.stream_id, j.req.init,
+                                   s->arena_base + off, lb, s->stream, &h);
+    if (st == ISING_OK) st = ising_set_beta(h, j.req.beta);
+    if (st != ISING_OK) {
+      s->arena.release(off, j.bytes);
+      if (h) ising_destroy(h);
+      return st;
+    }
+    j.h = h;
+    j.dev_series = (int64_t*)(s->arena_base + off + lb);
+    j.state = State::Active;
+    j.res.t_admit = now_s();
+    s->active.push_back(j.ticket);
+    s->queue.pop_front();
+    ++s->admitted;
+    s->peak = std::max<int64_t>(s->peak, (int64_t)s->arena.used());
+  }
+  return ISING_OK;
+}
+
+// Exact sums of M^2 and M^4 over the kept sweeps, rounded once to double.
+void moments(const int64_t* series, int64_t n, int64_t discard, ising_result* r) {
+  unsigned __int128 s2 = 0, s4 = 0;
+  int64_t kept = 0;
+  for (int64_t k = std::max<int64_t>(discard, 0); k < n; ++k) {
+    const __int128 m = series[2 * k + 1];
+    const unsigned __int128 m2 = (unsigned __int128)(m * m);
+    s2 += m2;
+    s4 += m2 * m2;
+    ++kept;
+  }
+  r->sum_M2 = (double)s2;
+  r->sum_M4 = (double)s4;
+  r->n_kept = kept;
+}
+
+ising_status retire(ising_server* s, Job& j) {
+  std::vector<int64_t> series((size_t)j.req.n_sweeps * 2);
+  hipError_t e = hipMemcpyAsync(series.data(), j.dev_series, series.size() * sizeof(int64_t),
+                                hipMemcpyDeviceToHost, s->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  if (e != hipSuccess) return hip_fail(e, "server: series copy");
+  if ((j.req.flags & ISING_REQ_RECORD_SERIES) && j.req.EM_series)
+    std::memcpy(j.req.EM_series, series.data(), series.size() * sizeof(int64_t));
+  if ((j.req.flags & ISING_REQ_RETURN_SPINS) && j.req.spins_out) {
+    ising_status st = ising_get_spins(j.h, j.req.spins_out);
+    if (st != ISING_OK) return st;
+  }
+  j.res.E_final = series[series.size() - 2];
+  j.res.M_final = series[series.size() - 1];
+  j.res.sweeps_done = (uint64_t)j.done;
+  moments(series.data(), j.req.n_sweeps, j.req.n_discard, &j.res);
+  j.res.status = ISING_OK;
+  j.res.t_done = now_s();
+  ising_destroy(j.h);
+  j.h = nullptr;
+  s->arena.release(j.off, j.bytes);
+  j.state = State::Done;
+  ++s->finished;
+  return ISING_OK;
+}
+
+// One batched call over the active set; each lattice takes up to Q sweeps.
+ising_status run_quantum(ising_server* s, std::vector<ising_lattice*>& hs,
+                         std::vector<int64_t>& nsw, std::vector<int64_t*>& ems, int64_t n) {
+  BatchOptions opt = default_batch_options();
+  ising_status st = batch_sweeps(hs.data(), (int32_t)hs.size(), n, nsw.data(), ems.data(), opt,
+                                 nullptr);
+  if (st != ISING_OK) return st;
+  hipError_t e = hipStreamSynchronize(s->stream);
+  return e == hipSuccess ? ISING_OK : hip_fail(e, "server: quantum");
+}
+
+ising_status step(ising_server* s) {
+  ising_status st = admit(s);
+  if (st != ISING_OK) return st;
+  if (s->active.empty()) return s->queue.empty() ? ISING_OK : ISING_AGAIN;
+  std::vector<ising_lattice*> hs;
+  std::vector<int64_t> nsw;
+  std::vector<int64_t*> ems;
+  int64_t n = 0;
+  for (uint64_t t : s->active) {
+    Job& j = s->jobs.at(t);
+    const int64_t take = std::min<int64_t>(s->quantum, j.req.n_sweeps - j.done);
+    hs.push_back(j.h);
+    nsw.push_back(take);
+    ems.push_back(j.dev_series + 2 * j.done);
+    n = std::max(n, take);
+  }
+  const int64_t q = s->quanta++;
+  if (s->faults.count(q)) {
+    // snapshot, run, declare the quantum failed, restore, run again
+    std::vector<std::vector<char>> snap(hs.size());
+    for (size_t i = 0; i < hs.size(); ++i) {
+      snap[i].resize(2 * (size_t)hs[i]->plane_words * sizeof(uint64_t));
+      hipError_t e = hipMemcpyAsync(snap[i].data(), hs[i]->planes, snap[i].size(),
+                                    hipMemcpyDeviceToHost, s->stream);
+      if (e != hipSuccess) return hip_fail(e, "server: snapshot");
+    }
+    st = run_quantum(s, hs, nsw, ems, n);
+    if (st != ISING_OK) return st;
+    for (size_t i = 0; i < hs.size(); ++i) {
+      hipError_t e = hipMemcpyAsync(hs[i]->planes, snap[i].data(), snap[i].size(),
+                                    hipMemcpyHostToDevice, s->stream);
+      if (e != hipSuccess) return hip_fail(e, "server: restore");
+    }
+    s->faults.erase(q);
+    ++s->recovered;
+  }
+  st = run_quantum(s, hs, nsw, ems, n);
+  if (st != ISING_OK) return st;
+  std::vector<uint64_t> still;
+  for (size_t i = 0; i < s->active.size(); ++i) {
+    Job& j = s->jobs.at(s->active[i]);
+    j.h->sweep += (uint64_t)nsw[i];
+    j.done += nsw[i];
+    if (j.done >= j.req.n_sweeps) {
+      st = retire(s, j);
+      if (st != ISING_OK) return st;
+    } else {
+      still.push_back(j.ticket);
+    }
+  }
+  s->active.swap(still);
+  return (s->active.empty() && s->queue.empty()) ? ISING_OK : ISING_AGAIN;
+}
+
+}  // namespace
+}  // namespace ising
+
 extern "C" {
-ising_status ising_server_create(void*, size_t, void*, int32_t, ising_server_t** out) {
-  if (out) *out = nullptr;
-  return fail(ISING_EINVAL, "served mode is not available in this build");
+
+ising_status ising_server_create(void* dev_arena, size_t arena_bytes, void* hip_stream,
+                                 int32_t quantum_sweeps, ising_server_t** out) {
+  clear_error();
+  if (!out) return fail(ISING_EINVAL, "ising_server_create: out is NULL");
+  *out = nullptr;
+  if (!dev_arena || arena_bytes < 256 || ((uintptr_t)dev_arena & 255))
+    return fail(ISING_EINVAL, "ising_server_create: arena must be non-NULL, 256-B aligned");
+  if (quantum_sweeps < 1)
+    return fail(ISING_EINVAL, "ising_server_create: quantum_sweeps must be >= 1");
+  ising_server* s = new (std::nothrow) ising_server(arena_bytes & ~(size_t)255);
+  if (!s) return fail(ISING_ENOMEM, "ising_server_create: host allocation failed");
+  s->arena_base = (char*)dev_arena;
+  s->arena_bytes = arena_bytes & ~(size_t)255;
+  s->stream = (hipStream_t)hip_stream;
+  s->quantum = quantum_sweeps;
+  *out = s;
+  return ISING_OK;
 }
-ising_status ising_batch_submit(ising_server_t*, const ising_request*, int32_t, uint64_t*) {
-  return fail(ISING_EINVAL, "served mode is not available in this build");
+
+ising_status ising_batch_submit(ising_server_t* s, const ising_request* reqs, int32_t n,
+                                uint64_t* tickets_out) {
+  clear_error();
+  if (!s || (n > 0 && (!reqs || !tickets_out)) || n < 0)
+    return fail(ISING_EINVAL, "ising_batch_submit: bad arguments");
+  // validate all first: nothing is queued if any request is invalid
+  for (int32_t i = 0; i < n; ++i) {
+    const ising_request& r = reqs[i];
+    if (lattice_bytes(r.L) == 0)
+      return fail(ISING_EINVAL, "ising_batch_submit: request %d: bad L=%lld", i, (long long)r.L);
+    if (std::isnan(r.beta) || r.beta < 0)
+      return fail(ISING_EINVAL, "ising_batch_submit: request %d: bad beta", i);
+    if (r.init < 0 || r.init > 2 || r.stream_id >= (1u << 30) || r.n_sweeps < 1 ||
+        r.n_sweeps >= (int64_t(1) << 32) || r.n_discard < 0)
+      return fail(ISING_EINVAL, "ising_batch_submit: request %d: bad init/stream/sweeps", i);
+    if ((r.flags & ISING_REQ_RECORD_SERIES) && !r.EM_series)
+      return fail(ISING_EINVAL, "ising_batch_submit: request %d: series buffer missing", i);
+    if ((r.flags & ISING_REQ_RETURN_SPINS) && !r.spins_out)
+      return fail(ISING_EINVAL, "ising_batch_submit: request %d: spins buffer missing", i);
+    if (job_bytes(r) > s->arena_bytes)
+      return fail(ISING_ENOMEM, "ising_batch_submit: request %d needs %zu bytes > arena %zu", i,
+                  job_bytes(r), s->arena_bytes);
+  }
+  const double t = now_s();
+  for (int32_t i = 0; i < n; ++i) {
+    Job j;
+    j.ticket = s->next_ticket++;
+    j.req = reqs[i];
+    j.bytes = job_bytes(reqs[i]);
+    std::memset(&j.res, 0, sizeof(j.res));
+    j.res.ticket = j.ticket;
+    j.res.status = ISING_AGAIN;
+    j.res.t_arrive = t;
+    s->jobs.emplace(j.ticket, j);
+    s->queue.push_back(j.ticket);
+    tickets_out[i] = j.ticket;
+  }
+  return ISING_OK;
 }
-ising_status ising_server_step(ising_server_t*) {
-  return fail(ISING_EINVAL, "served mode is not available in this build");
+
+ising_status ising_server_step(ising_server_t* s) {
+  clear_error();
+  if (!s) return fail(ISING_EINVAL, "ising_server_step: NULL server");
+  return step(s);
 }
-ising_status ising_poll(ising_server_t*, uint64_t, ising_result*) {
-  return fail(ISING_EINVAL, "served mode is not available in this build");
+
+ising_status ising_poll(ising_server_t* s, uint64_t ticket, ising_result* out) {
+  clear_error();
+  if (!s || !out) return fail(ISING_EINVAL, "ising_poll: NULL argument");
+  auto it = s->jobs.find(ticket);
+  if (it == s->jobs.end()) return fail(ISING_ENOTFOUND, "ising_poll: unknown ticket %llu",
+                                       (unsigned long long)ticket);
+  *out = it->second.res;
+  if (it->second.state != State::Done) {
+    out->status = ISING_AGAIN;
+    out->sweeps_done = (uint64_t)it->second.done;
+    return ISING_AGAIN;
+  }
+  s->jobs.erase(it);
+  return ISING_OK;
 }
-ising_status ising_server_inject_fault(ising_server_t*, int64_t) {
-  return fail(ISING_EINVAL, "served mode is not available in this build");
+
+ising_status ising_server_inject_fault(ising_server_t* s, int64_t quantum_index) {
+  clear_error();
+  if (!s || quantum_index < 0) return fail(ISING_EINVAL, "ising_server_inject_fault: bad args");
+  s->faults.insert(quantum_index);
+  return ISING_OK;
 }
-ising_status ising_server_stats(const ising_server_t*, int64_t*) {
-  return fail(ISING_EINVAL, "served mode is not available in this build");
+
+ising_status ising_server_stats(const ising_server_t* s, int64_t out[6]) {
+  clear_error();
+  if (!s || !out) return fail(ISING_EINVAL, "ising_server_stats: NULL argument");
+  out[0] = s->quanta;
+  out[1] = s->admitted;
+  out[2] = s->finished;
+  out[3] = (int64_t)s->arena.used();
+  out[4] = s->peak;
+  out[5] = s->recovered;
+  return ISING_OK;
 }
-ising_status ising_server_destroy(ising_server_t*) { return ISING_OK; }
+
+ising_status ising_server_destroy(ising_server_t* s) {
+  clear_error();
+  if (!s) return ISING_OK;
+  for (auto& kv : s->jobs)
+    if (kv.second.h) ising_destroy(kv.second.h);
+  delete s;
+  return ISING_OK;
 }
+
+}  // extern "C"

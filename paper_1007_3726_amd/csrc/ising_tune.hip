@@ -16,8 +16,8 @@ PlanModel default_model() {
   PlanModel m;
   m.wg_per_cu = 8;          // 16.4 KB LDS and <= 64 VGPRs per lane allow 8 per CU
   m.tile_s_full = 13e-6;    // ~1000 VALU instructions per lane, 8 waves per SIMD
-  m.tile_s_alone = 2.5e-6;  // one wave per SIMD: issue plus memory latency
-  m.launch_gap_s = 4e-6;
+  m.tile_s_alone = 4.5e-6;  // one wave per SIMD: issue plus memory latency (measured)
+  m.launch_gap_s = 5e-6;    // dependent launches replayed from a graph (measured)
   return m;
 }
 

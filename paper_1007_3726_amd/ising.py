@@ -243,3 +243,92 @@ def multi_sweep(lattices: Sequence[Lattice], n: int, EMs=None, form=None, graph_
             *[(e.data_ptr() if e is not None else None) for e in EMs])
     f = {None: -1, "fused": 0, "packed": 1}[form]
     check(lib().ising_multi_sweep_form(arr, len(lattices), int(n), em_arr, f, int(graph_chunk)))
+
+
+class Server:
+    """Continuous-batching server over a device arena (a torch uint8 tensor)."""
+
+    def __init__(self, arena_bytes: int, quantum_sweeps: int = 100, device="cuda", stream=None):
+        import torch
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.arena = _dev_alloc(arena_bytes, self.device)
+        s = ctypes.c_void_p()
+        check(lib().ising_server_create(self.arena.data_ptr(), int(arena_bytes),
+                                        _stream_ptr(self.stream), int(quantum_sweeps),
+                                        ctypes.byref(s)))
+        self.s = s
+        self._buffers = {}
+
+    def close(self):
+        if getattr(self, "s", None):
+            lib().ising_server_destroy(self.s)
+            self.s = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, requests):
+        """requests: iterable of dicts with L, beta, seed, stream_id, init, n_sweeps and
+        optional n_discard, record_series, return_spins.  Returns the tickets."""
+        requests = list(requests)
+        arr = (ising_request * max(len(requests), 1))()
+        keep = []
+        for i, r in enumerate(requests):
+            q = arr[i]
+            q.L, q.beta, q.seed = int(r["L"]), float(r["beta"]), int(r.get("seed", 1))
+            q.stream_id, q.init = int(r.get("stream_id", 0)), int(r.get("init", INIT_HOT))
+            q.n_sweeps, q.n_discard = int(r["n_sweeps"]), int(r.get("n_discard", 0))
+            flags = 0
+            series = spins = None
+            if r.get("record_series"):
+                flags |= REQ_RECORD_SERIES
+                series = np.zeros((q.n_sweeps, 2), dtype=np.int64)
+                q.EM_series = series.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+            if r.get("return_spins"):
+                flags |= REQ_RETURN_SPINS
+                spins = np.zeros((q.L, q.L), dtype=np.int8)
+                q.spins_out = spins.ctypes.data_as(ctypes.POINTER(ctypes.c_int8))
+            q.flags = flags
+            keep.append((series, spins))
+        tickets = (ctypes.c_uint64 * max(len(requests), 1))()
+        check(lib().ising_batch_submit(self.s, arr, len(requests), tickets))
+        out = [int(tickets[i]) for i in range(len(requests))]
+        for t, k in zip(out, keep):
+            self._buffers[t] = k
+        return out
+
+    def step(self) -> bool:
+        """One quantum; True while work remains."""
+        return check(lib().ising_server_step(self.s), ok=(ISING_OK, ISING_AGAIN)) == ISING_AGAIN
+
+    def poll(self, ticket: int):
+        """None while running; else a dict with the result (and series/spins if requested)."""
+        r = ising_result()
+        code = check(lib().ising_poll(self.s, int(ticket), ctypes.byref(r)),
+                     ok=(ISING_OK, ISING_AGAIN))
+        if code == ISING_AGAIN:
+            return None
+        series, spins = self._buffers.pop(int(ticket), (None, None))
+        return {"ticket": int(r.ticket), "E_final": int(r.E_final), "M_final": int(r.M_final),
+                "sweeps_done": int(r.sweeps_done), "sum_M2": float(r.sum_M2),
+                "sum_M4": float(r.sum_M4), "n_kept": int(r.n_kept), "t_arrive": r.t_arrive,
+                "t_admit": r.t_admit, "t_done": r.t_done, "series": series, "spins": spins}
+
+    def inject_fault(self, quantum_index: int):
+        check(lib().ising_server_inject_fault(self.s, int(quantum_index)))
+
+    def stats(self):
+        out = (ctypes.c_int64 * 6)()
+        check(lib().ising_server_stats(self.s, out))
+        keys = ["quanta", "admitted", "done", "bytes_in_use", "peak_bytes", "faults_recovered"]
+        return dict(zip(keys, [int(v) for v in out]))
+
+    def run_until_idle(self, max_steps: int = 10 ** 9):
+        for _ in range(max_steps):
+            if not self.step():
+                return
+        raise RuntimeError("server did not become idle")

@@ -1,0 +1,134 @@
+"""Served mode: continuous batching with HBM-budget admission.
+
+Each request's result (per-sweep E/M series and final spins) must be
+bit-identical whether it runs alone or in a mix admitted as memory frees,
+with or without an injected (host-forced) quantum failure; admission never
+exceeds the arena; oversized or invalid requests are rejected.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def I():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1007_3726_amd import ising
+    ising.lib()
+    return ising
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _requests():
+    rng = np.random.default_rng(5)
+    reqs = []
+    for i, L in enumerate([32, 64, 96, 128, 160, 256, 320, 512, 34, 1024, 64, 2048]):
+        reqs.append({"L": L, "beta": 1.0 / float(rng.uniform(1.5, 3.5)), "seed": 1000 + i,
+                     "stream_id": 0, "init": workloads.INIT_HOT,
+                     "n_sweeps": int(rng.integers(5, 40)), "n_discard": 2,
+                     "record_series": True, "return_spins": True})
+    return reqs
+
+
+def _run(I, reqs, arena_bytes, quantum, fault_at=None):
+    srv = I.Server(arena_bytes, quantum_sweeps=quantum)
+    if fault_at is not None:
+        srv.inject_fault(fault_at)
+    tickets = srv.submit(reqs)
+    srv.run_until_idle()
+    results = [srv.poll(t) for t in tickets]
+    stats = srv.stats()
+    srv.close()
+    return results, stats
+
+
+def test_alone_equals_mix(I):
+    reqs = _requests()
+    need = max(I.ising_lattice_bytes(r["L"]) for r in reqs) + (4 << 20)
+    _say("case alone")
+    alone = [_run(I, [r], need, 6)[0][0] for r in reqs]
+    _say("case mix (small arena forces queueing)")
+    mix, stats = _run(I, reqs, 3 * need // 2, 6)
+    assert stats["done"] == len(reqs) and stats["admitted"] == len(reqs)
+    assert stats["peak_bytes"] <= 3 * need // 2
+    for r, a, m in zip(reqs, alone, mix):
+        assert np.array_equal(a["series"], m["series"]), r
+        assert np.array_equal(a["spins"], m["spins"]), r
+        assert (a["E_final"], a["M_final"]) == (m["E_final"], m["M_final"])
+        assert m["sweeps_done"] == r["n_sweeps"]
+
+
+def test_requests_match_plain_path_and_oracle(I):
+    reqs = _requests()
+    res, _ = _run(I, reqs, 64 << 20, 9)
+    for r, got in zip(reqs, res):
+        lat = I.Lattice(r["L"], seed=r["seed"], stream_id=r["stream_id"], init=r["init"],
+                        beta=r["beta"])
+        em = lat.sweep_em(r["n_sweeps"]).cpu().numpy()
+        assert np.array_equal(got["series"], em), r
+        assert np.array_equal(got["spins"], lat.get_spins())
+        if r["L"] <= 128:
+            s, oEM = oracle.run(r["L"], r["beta"], r["seed"], r["stream_id"], r["init"],
+                                r["n_sweeps"])
+            assert np.array_equal(got["series"], oEM)
+            assert np.array_equal(got["spins"], s)
+        M = [int(v) for v in em[r["n_discard"]:, 1]]
+        assert got["n_kept"] == len(M)
+        assert got["sum_M2"] == float(sum(v * v for v in M))
+        assert got["sum_M4"] == float(sum(v ** 4 for v in M))
+
+
+def test_fault_injection_recovers_bit_identically(I):
+    reqs = _requests()[:8]
+    clean, _ = _run(I, reqs, 64 << 20, 5)
+    faulty, stats = _run(I, reqs, 64 << 20, 5, fault_at=2)
+    assert stats["faults_recovered"] == 1
+    for a, b in zip(clean, faulty):
+        assert np.array_equal(a["series"], b["series"])
+        assert np.array_equal(a["spins"], b["spins"])
+
+
+def test_fifo_admission_and_budget(I):
+    reqs = [{"L": 256, "beta": 0.4, "seed": i, "n_sweeps": 10 + i} for i in range(6)]
+    one = I.ising_lattice_bytes(256) + 16 * 20 + 512
+    srv = I.Server(2 * one, quantum_sweeps=4)
+    tickets = srv.submit(reqs)
+    seen_peak = 0
+    while srv.step():
+        seen_peak = max(seen_peak, srv.stats()["bytes_in_use"])
+    res = [srv.poll(t) for t in tickets]
+    st = srv.stats()
+    assert st["peak_bytes"] <= 2 * one and seen_peak <= 2 * one
+    admits = [r["t_admit"] for r in res]
+    assert admits == sorted(admits), "admission is not FIFO"
+    srv.close()
+
+
+def test_rejections(I):
+    srv = I.Server(1 << 20, quantum_sweeps=4)
+    with pytest.raises(I.IsingError) as e:
+        srv.submit([{"L": 4096, "beta": 0.4, "n_sweeps": 10}])  # larger than the arena
+    assert e.value.code == I.ISING_ENOMEM
+    with pytest.raises(I.IsingError):
+        srv.submit([{"L": 64, "beta": 0.4, "n_sweeps": 5},
+                    {"L": 63, "beta": 0.4, "n_sweeps": 5}])  # odd L: nothing queued
+    with pytest.raises(I.IsingError):
+        srv.submit([{"L": 64, "beta": -1.0, "n_sweeps": 5}])
+    assert srv.stats()["admitted"] == 0
+    assert not srv.step()
+    with pytest.raises(I.IsingError) as e:
+        srv.poll(12345)
+    assert e.value.code == I.ISING_ENOTFOUND
+    srv.close()
