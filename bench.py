@@ -47,7 +47,107 @@ def parse():
     p.add_argument("--no-batched", action="store_true",
                    help="skip the batched finite-size-scaling grid")
     p.add_argument("--batched-sweeps", type=int, default=workloads.FSS_SWEEPS)
+    p.add_argument("--no-served", action="store_true", help="skip the served request stream")
+    p.add_argument("--served-requests", type=int, default=200,
+                   help="requests of the 2000-request Poisson stream to serve (default: the "
+                        "first 200, about 20 s)")
+    p.add_argument("--served-arena-gib", type=float, default=1.0)
+    p.add_argument("--served-quantum", type=int, default=200)
+    p.add_argument("--plain-fifo-requests", type=int, default=20,
+                   help="requests of the same stream run one by one with the plain path")
     return p.parse_args()
+
+
+def bench_served(torch, ising, dev, n_req, arena_gib, quantum, plain_n, plain_rate):
+    """Poisson stream of requests (L log-uniform in [32, 8192], T uniform in
+    [1.5, 3.5], sweeps log-uniform in [1e3, 1e5], seed 1000 + i, hot start)
+    served with continuous batching; arrival rate 0.7 x the plain throughput
+    divided by the mean work per request (1.30e11 spin updates)."""
+    import numpy as np
+    rate = 0.7 * plain_rate * 1e9 / 1.30e11
+    stream = workloads.served_stream(2000, rate=rate)[:n_req]
+    srv = ising.Server(int(arena_gib * (1 << 30)), quantum_sweeps=quantum, device=dev)
+    t0 = time.perf_counter()
+    t0_abs = _monotonic_now()
+    nxt = 0
+    pending = {}
+    lat = []
+    work_done = 0
+    t_last = 0.0
+    last_note = time.perf_counter()
+    while nxt < len(stream) or pending:
+        now = time.perf_counter() - t0
+        if time.perf_counter() - last_note > 5.0:
+            print("bench: served t=%.0fs submitted=%d finished=%d in flight=%d"
+                  % (now, nxt, len(lat), len(pending)), file=sys.stderr, flush=True)
+            last_note = time.perf_counter()
+        batch = []
+        while nxt < len(stream) and stream[nxt].arrival <= now:
+            batch.append(stream[nxt])
+            nxt += 1
+        if batch:
+            reqs = [{"L": r.L, "beta": 1.0 / r.T, "seed": r.seed, "stream_id": r.stream_id,
+                     "init": r.init, "n_sweeps": r.sweeps, "n_discard": r.sweeps // 5}
+                    for r in batch]
+            for r, t in zip(batch, srv.submit(reqs)):
+                pending[t] = r
+        busy = srv.step() if pending else False
+        for t in list(pending):
+            res = srv.poll(t)
+            if res is not None:
+                r = pending.pop(t)
+                # latency from the scheduled arrival (queueing included)
+                lat.append(res["t_done"] - (t0_abs + r.arrival))
+                work_done += r.L * r.L * r.sweeps
+                t_last = max(t_last, res["t_done"])
+        if not busy and not pending and nxt < len(stream):
+            time.sleep(max(0.0, stream[nxt].arrival - (time.perf_counter() - t0)))
+    wall = t_last - (t0_abs + stream[0].arrival)
+    stats = srv.stats()
+    srv.close()
+    lat = np.array(lat)
+    out = {"value": round(work_done / (wall * 1e9), 2), "unit": "spin updates/ns",
+           "requests": len(stream), "rate_per_s": round(rate, 3),
+           "p50_latency_s": round(float(np.percentile(lat, 50)), 3),
+           "p99_latency_s": round(float(np.percentile(lat, 99)), 3),
+           "mean_latency_s": round(float(lat.mean()), 3),
+           "wall_s": round(wall, 3), "arena_gib": arena_gib, "quantum_sweeps": quantum,
+           "peak_arena_bytes": stats["peak_bytes"], "quanta": stats["quanta"]}
+    # the same requests one at a time through the plain path (FIFO, no overlap)
+    if plain_n > 0:
+        sub = stream[:plain_n]
+        tp = time.perf_counter()
+        clock = 0.0
+        plat = []
+        pwork = 0
+        for j, r in enumerate(sub):
+            if j % 5 == 0:
+                print("bench: plain FIFO request %d/%d" % (j, plain_n), file=sys.stderr,
+                      flush=True)
+            L = ising.Lattice(r.L, seed=r.seed, stream_id=r.stream_id, init=r.init,
+                              beta=1.0 / r.T, device=dev)
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            L.sweep(r.sweeps)
+            torch.cuda.synchronize()
+            svc = time.perf_counter() - a
+            clock = max(clock, r.arrival) + svc
+            plat.append(clock - r.arrival)
+            pwork += r.L * r.L * r.sweeps
+            del L
+        busy_s = time.perf_counter() - tp
+        plat = np.array(plat)
+        out["plain_fifo"] = {"requests": plain_n, "value": round(pwork / (clock - sub[0].arrival)
+                                                                 / 1e9, 2),
+                             "service_rate": round(pwork / (busy_s * 1e9), 2),
+                             "p50_latency_s": round(float(np.percentile(plat, 50)), 3),
+                             "p99_latency_s": round(float(np.percentile(plat, 99)), 3)}
+    return out
+
+
+def _monotonic_now():
+    """The library's clock for t_arrive/t_admit/t_done (steady clock, seconds)."""
+    return time.monotonic()
 
 
 def binder_exact(M, discard):
@@ -194,6 +294,12 @@ def main():
               flush=True)
         del EM
         result["batched"] = bench_batched(torch, ising, dev, args.batched_sweeps)
+    if not args.no_served:
+        print("bench: served stream (%d requests)" % args.served_requests, file=sys.stderr,
+              flush=True)
+        result["served"] = bench_served(torch, ising, dev, args.served_requests,
+                                        args.served_arena_gib, args.served_quantum,
+                                        args.plain_fifo_requests, value)
     if not args.no_cpu_baseline:
         print("bench: CPU oracle baseline (%d sweeps)" % args.cpu_sweeps, file=sys.stderr,
               flush=True)

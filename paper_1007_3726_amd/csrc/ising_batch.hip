@@ -323,8 +323,8 @@ extern "C" ising_status ising_batch_plan(const int64_t* Ls, int32_t count, int32
     if (L < 8 || L % 8 || L > kMaxL)
       return fail(ISING_EINVAL, "ising_batch_plan: L=%lld is not a tiled size", (long long)L);
     const int64_t W = words_per_row(L);
-    const int64_t R = W >= 64 ? 1 : 64 / W;
-    const int64_t segs = W >= 64 ? (W + 63) / 64 : 1;
+    const int64_t R = W >= kWideMinWords ? 1 : 64 / W;
+    const int64_t segs = W >= kWideMinWords ? (W + 63) / 64 : 1;
     tiles[i] = ((L + 4 * R - 1) / (4 * R)) * segs;
   }
   const BatchPlan plan = plan_batch(tiles, cus, default_model());

@@ -225,7 +225,7 @@ __global__ __launch_bounds__(1024) void k_small_sweeps(SmallArgs a) {
 //
 // Work unit: a tile of TR = 4*R*RPW rows x TW words of colour C.  A wave
 // processes RPW row groups of the tile one after the other, one word per
-// lane per group (W >= 64: a row group is one row of a 64-word segment;
+// lane per group (W >= kWideMinWords: a row group is one row of a 64-word segment;
 // W < 64: a row group is R = floor(64/W) whole rows).  The other colour's
 // rows y0-1 .. y0+TR and words w0-1 .. w0+TW (periodic) are staged in LDS
 // with coalesced loads, so each neighbour word is read from HBM/L2 about
@@ -288,8 +288,8 @@ template <int WIDEM>
 __device__ __forceinline__ TileLane tile_lane(const TileArgs& a) {
   TileLane t;
   // WIDEM: 0 / 1 fixes the row-group shape at compile time, 2 reads it from
-  // the arguments (W >= 64).
-  const bool WIDE = WIDEM == 2 ? (a.g.W >= 64) : (WIDEM == 1);
+  // the arguments (W >= kWideMinWords).
+  const bool WIDE = WIDEM == 2 ? (a.g.W >= kWideMinWords) : (WIDEM == 1);
   t.wide = WIDE;
   const int lane = threadIdx.x & 63;
   const int TW = a.TW, R = a.R;
@@ -313,6 +313,8 @@ __device__ __forceinline__ TileLane tile_lane(const TileArgs& a) {
     t.st_r = lane / t.SW;
     t.st_c = lane - t.st_r * t.SW;
     if (t.st_r >= t.P) t.st_r = -1;
+    // hosts only build narrow shapes with SW <= 64; never let a pass be empty
+    if (t.P < 1) t.P = 1;
   }
   return t;
 }
@@ -579,7 +581,7 @@ hipError_t launch_advance(hipStream_t st, uint32_t* kbase, uint32_t by) {
 hipError_t launch_tile_sweep(hipStream_t st, int colour, const TileArgs& a, int blocks) {
   const bool em = (colour == 1) ? (a.part != nullptr) : false;
   const bool full = a.g.nb_last == 64;
-  const bool wide = a.g.W >= 64;
+  const bool wide = a.g.W >= kWideMinWords;
 #define ISING_TILE(C, E, F, WI) \
   hipLaunchKernelGGL((k_tile_sweep<C, E, F, WI>), dim3(blocks), dim3(256), 0, st, a)
 #define ISING_TILE_FW(C, E)                                   \

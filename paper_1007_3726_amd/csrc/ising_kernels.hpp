@@ -32,6 +32,10 @@ struct SmallArgs {
 // of 4*R rows x TW words of one colour; the neighbour rows of the other
 // colour are staged in LDS once per tile.
 constexpr int kTileLdsMaxWords = 2048;
+// Rows of at least this many words use the wide tile shape (64-word row
+// segments).  A narrow tile stages whole rows of W + 2 words, and each such
+// row must fit one 64-lane wave pass, so narrow tiles need W <= 62.
+constexpr int kWideMinWords = 63;
 constexpr int kMaxSweepBlocks = 2048;
 
 struct TileArgs {
@@ -39,8 +43,8 @@ struct TileArgs {
   int64_t plane_words;
   Geom g;
   uint32_t k0, k1, sid4, t, t4, t8;
-  int32_t TW;       // tile width in words: 64 when W >= 64, else W
-  int32_t R;        // rows per row group: 1 when W >= 64, else floor(64 / W)
+  int32_t TW;       // tile width in words: 64 when W >= kWideMinWords, else W
+  int32_t R;        // rows per row group: 1 when W >= kWideMinWords, else floor(64 / W)
   int32_t RPW;      // row groups per wave in one tile
   int32_t segs;     // 64-word segments per row (1 when W < 64)
   int64_t tiles;    // ceil(L / (4 R RPW)) * segs

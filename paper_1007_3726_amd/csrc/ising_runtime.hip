@@ -95,7 +95,7 @@ bool tile_args(const ising_lattice* h, TileArgs* out) {
   if (L % 8 != 0) return false;
   TileArgs a;
   std::memset(&a, 0, sizeof(a));
-  const bool wide = W >= 64;
+  const bool wide = W >= kWideMinWords;
   a.TW = wide ? 64 : (int32_t)W;
   a.R = wide ? 1 : (int32_t)(64 / W);
   a.segs = wide ? (int32_t)((W + 63) / 64) : 1;
@@ -112,6 +112,8 @@ bool tile_args(const ising_lattice* h, TileArgs* out) {
   const int64_t TR = 4 * (int64_t)a.R * a.RPW;
   a.tiles = ((L + TR - 1) / TR) * a.segs;
   if ((TR + 2) * (a.TW + 2) > kTileLdsMaxWords) return false;
+  // a narrow staged row (W + 2 words) must fit one 64-lane wave pass
+  if (!wide && a.TW + 2 > 64) return false;
   const bool pow2 = (L & (L - 1)) == 0;
   if ((uint64_t)L * (uint64_t)L / 8 <= (1ull << 32))
     a.hi_mode = 0;

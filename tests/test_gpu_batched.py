@@ -119,3 +119,11 @@ def test_batched_errors(I):
     I.multi_sweep([], 3)
     I.multi_sweep([a], 0)
     assert a.sweep_count == 0
+
+
+@pytest.mark.parametrize("form", ["fused", "packed"])
+def test_batched_rows_of_62_to_64_words(I, form):
+    H = workloads.INIT_HOT
+    specs = [(7936, 2.3, 1, 1, H), (8000, 2.4, 2, 2, H), (8064, 2.5, 3, 3, H), (96, 2.0, 4, 4, H)]
+    _say("case batched W=62..63 form=%s" % form)
+    _batched_vs_plain(I, specs, 2, form=form)

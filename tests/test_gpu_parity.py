@@ -203,3 +203,21 @@ def test_error_paths(I):
     lat.sweep(2)
     assert lat.sweep_count == 2 ** 32
     lat.sweep(0)
+
+
+@pytest.mark.parametrize("L", [7936, 8000, 8064, 8192])
+def test_rows_of_62_to_64_words(I, L):
+    """W = 62, 63, 63, 64 words per row: the narrow/wide tile-shape boundary.
+    Full-lattice (E, M) against the oracle for 2 sweeps, and windows that
+    include the row seam and the periodic wrap."""
+    n = 2
+    beta = 1 / 2.4
+    _say("case L=%d (W=%d)" % (L, ((L // 2) + 63) // 64))
+    lat = I.Lattice(L, seed=13, stream_id=2, init=workloads.INIT_HOT, beta=beta)
+    gEM = lat.sweep_em(n).cpu().numpy()
+    s, oEM = oracle_series(L, beta, 13, 2, workloads.INIT_HOT, n)
+    assert np.array_equal(gEM, oEM)
+    for (x0, y0) in [(0, 0), (L - 20, L - 9), (L // 2 - 3, 17)]:
+        win = lat.get_window(x0, y0, 24, 12)
+        ref = s[-1][np.ix_([(y0 + j) % L for j in range(12)], [(x0 + i) % L for i in range(24)])]
+        assert np.array_equal(win, ref)
