@@ -47,6 +47,10 @@ def parse():
     p.add_argument("--no-batched", action="store_true",
                    help="skip the batched finite-size-scaling grid")
     p.add_argument("--batched-sweeps", type=int, default=workloads.FSS_SWEEPS)
+    p.add_argument("--workload", default="large", choices=["large", "huge-T2", "huge-T3", "small",
+                                                           "paper-4096"],
+                   help="plain workload: large = 16384^2 (the headline), huge = 262144^2 "
+                        "(8 GiB, HBM-resident), small = 64^2, paper-4096 = 4096^2 at 0.99 T_c")
     p.add_argument("--no-served", action="store_true", help="skip the served request stream")
     p.add_argument("--served-requests", type=int, default=200,
                    help="requests of the 2000-request Poisson stream to serve (default: the "
@@ -145,6 +149,40 @@ def bench_served(torch, ising, dev, n_req, arena_gib, quantum, plain_n, plain_ra
     return out
 
 
+def kernel_sources_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("ising_device.hpp", "ising_kernels.hpp", "ising_kernels.hip"):
+        with open(os.path.join(ROOT, "paper_1007_3726_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def profiled_traffic(workload_name):
+    """HBM bytes per launch from the committed rocprofv3 summary of this
+    workload (FETCH_SIZE + WRITE_SIZE scaled by a plain copy), or None when the
+    summary is missing or the kernels changed since it was taken."""
+    name = {"large": "k_tile_sweep_plain-16384.txt",
+            "huge-T2": "k_tile_sweep_plain-262144.txt"}.get(workload_name)
+    if name is None:
+        return None
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as fh:
+        for line in fh:
+            if ": " in line and not line.startswith(("#", " ", "|")):
+                k, v = line.rstrip("\n").split(": ", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha256") != kernel_sources_sha():
+        return None
+    try:
+        return int(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def _monotonic_now():
     """The library's clock for t_arrive/t_admit/t_done (steady clock, seconds)."""
     return time.monotonic()
@@ -209,8 +247,8 @@ def cpu_baseline(w, sweeps):
     dt = time.perf_counter() - t0
     ups = w.L * w.L * sweeps / (dt * 1e9)
     return {"value": ups, "unit": "spin updates/ns", "cores": threads, "kind": "oracle",
-            "sample": "%d sweeps of the %dx%d lattice (cold start, T=%r), %.1f s"
-                      % (sweeps, w.L, w.L, w.T, dt)}
+            "sample": "%d sweeps of the %dx%d lattice (%s start, T=%r), %.1f s"
+                      % (sweeps, w.L, w.L, ["cold +1", "cold -1", "hot"][w.init], w.T, dt)}
 
 
 def main():
@@ -222,7 +260,8 @@ def main():
     import torch
     from paper_1007_3726_amd import ising
 
-    w = workloads.LARGE
+    w = {"large": workloads.LARGE, "huge-T2": workloads.HUGE_T2, "huge-T3": workloads.HUGE_T3,
+         "small": workloads.SMALL, "paper-4096": workloads.PAPER_POINT}[args.workload]
     if args.sweeps is not None:
         import dataclasses
         w = dataclasses.replace(w, sweeps=args.sweeps)
@@ -271,12 +310,16 @@ def main():
         "vs_baseline": None,
         "dtype": "u64",
         "data": "synthetic",
-        "config": {"workload": "plain %dx%d periodic lattice, T=%r, cold start, %d sweeps/step, "
-                               "per-sweep int64 E/M" % (w.L, w.L, w.T, w.sweeps),
+        "config": {"workload": "plain %dx%d periodic lattice, T=%r, %s start, %d sweeps/step, "
+                               "per-sweep int64 E/M" % (w.L, w.L, w.T,
+                                                        ["cold +1", "cold -1", "hot"][w.init],
+                                                        w.sweeps),
                    "L": w.L, "T": w.T, "sweeps_per_step": w.sweeps, "form": "plain"},
         "roofline": {"bound": "alu", "achieved": round(achieved / 1e12, 3),
                      "peak": round(VALU_PEAK_LANE_OPS / 1e12, 3), "unit": "Tops/s",
-                     "frac": round(achieved / VALU_PEAK_LANE_OPS, 4), "traffic": None,
+                     "frac": round(achieved / VALU_PEAK_LANE_OPS, 4),
+                     "traffic": profiled_traffic(args.workload),
+                     "algorithmic_bytes_per_launch": 3 * N // 16,
                      "kernel": "k_tile_sweep", "avg_launch_us": round(launch_us, 3),
                      "ops_per_update": ALU_OPS_PER_UPDATE},
         "wall_s": round(wall, 3),
@@ -300,7 +343,10 @@ def main():
         result["served"] = bench_served(torch, ising, dev, args.served_requests,
                                         args.served_arena_gib, args.served_quantum,
                                         args.plain_fifo_requests, value)
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and w.L > 65536:
+        print("bench: no CPU baseline for a %d^2 lattice (the byte-per-spin oracle would need "
+              "%.0f GB)" % (w.L, w.L * w.L / 1e9), file=sys.stderr, flush=True)
+    elif not args.no_cpu_baseline:
         print("bench: CPU oracle baseline (%d sweeps)" % args.cpu_sweeps, file=sys.stderr,
               flush=True)
         result["cpu_baseline"] = cpu_baseline(w, args.cpu_sweeps)
