@@ -268,6 +268,9 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream(dev)
+    # the autotuner picks the tile shape for this lattice size (a few hundred ms)
+    tuned = ising.autotune(w.L, trial_sweeps=max(2, min(50, int(4e9 / (w.L * w.L)))),
+                           device=dev, stream=stream)
     lat = ising.Lattice(w.L, seed=w.seed, stream_id=w.stream_id, init=w.init, beta=1.0 / w.T,
                         device=dev, stream=stream)
     EM = torch.empty((w.sweeps, 2), dtype=torch.int64, device=dev)
@@ -323,6 +326,8 @@ def main():
                      "kernel": "k_tile_sweep", "avg_launch_us": round(launch_us, 3),
                      "ops_per_update": ALU_OPS_PER_UPDATE},
         "wall_s": round(wall, 3),
+        "tuned_shape": {"rpw": tuned["rpw"], "max_blocks": tuned["max_blocks"],
+                        "lds_resident_bytes": tuned["small_lds_bytes"]},
     }
     if args.copy_calibration:
         # a plain copy of known size: 1 GiB read + 1 GiB written

@@ -178,6 +178,40 @@ ISING_API ising_status ising_batch_plan(const int64_t *Ls, int32_t count, int32_
                                         double *est_seconds_out);
 
 /* ---------------------------------------------------------------- */
+/* Autotuner: launch shapes of the plain sweep per lattice size class. */
+/* ---------------------------------------------------------------- */
+
+typedef struct {
+    int64_t L_min, L_max;    /* size class the entry applies to */
+    int32_t rpw;             /* row groups per wave in a tile (0: size rule) */
+    int32_t max_blocks;      /* grid cap, 1..2048 */
+    int64_t small_lds_bytes; /* lattices with both planes <= this run in one LDS-resident
+                                workgroup (0: never) */
+    double updates_per_ns;   /* rate measured by the autotuner (informational) */
+} ising_tuning;
+
+/*
+ * Time candidate shapes (LDS-resident single workgroup for small lattices;
+ * rpw in {1, 2, 4} x grid cap in {512, 1024, 2048}) of the plain sweep for a
+ * lattice of side L, using the caller's device buffer (ising_lattice_bytes(L)
+ * bytes) as scratch, trial_sweeps timed sweeps each; install the fastest for
+ * L's size class [2^k, 2^(k+1)) and return it in *out.  Handles created
+ * afterwards use it; results are bit-identical for every shape.
+ * Synchronises the stream.
+ */
+ISING_API ising_status ising_autotune(int64_t L, void *dev_buf, size_t dev_bytes, void *hip_stream,
+                                      int32_t trial_sweeps, ising_tuning *out);
+
+/* Install tuning entries (for example a cache written by an earlier run). */
+ISING_API ising_status ising_tuning_set(const ising_tuning *entries, int32_t count);
+
+/* Copy up to `capacity` installed entries; *count receives how many exist. */
+ISING_API ising_status ising_tuning_get(ising_tuning *entries, int32_t capacity, int32_t *count);
+
+/* Remove all installed entries (back to the defaults). */
+ISING_API ising_status ising_tuning_clear(void);
+
+/* ---------------------------------------------------------------- */
 /* Served mode: continuous batching of independent simulations.      */
 /* ---------------------------------------------------------------- */
 

@@ -99,14 +99,20 @@ bool tile_args(const ising_lattice* h, TileArgs* out) {
   a.TW = wide ? 64 : (int32_t)W;
   a.R = wide ? 1 : (int32_t)(64 / W);
   a.segs = wide ? (int32_t)((W + 63) / 64) : 1;
-  // row groups per wave: as many as keep >= 2048 tiles (8 per CU) and fit in LDS
+  // row groups per wave: the tuned value if it fits in LDS, else as many as
+  // keep >= 2048 tiles (8 per CU) and fit
   a.RPW = 1;
-  for (int rpw = 4; rpw > 1; rpw >>= 1) {
-    const int64_t TR = 4 * (int64_t)a.R * rpw;
-    const int64_t tiles = ((L + TR - 1) / TR) * a.segs;
-    if (tiles >= 2048 && (TR + 2) * (a.TW + 2) <= kTileLdsMaxWords) {
-      a.RPW = rpw;
-      break;
+  const int want = h->tune.rpw;
+  if (want > 0 && (4 * (int64_t)a.R * want + 2) * (a.TW + 2) <= kTileLdsMaxWords) {
+    a.RPW = want;
+  } else {
+    for (int rpw = 4; rpw > 1; rpw >>= 1) {
+      const int64_t TR = 4 * (int64_t)a.R * rpw;
+      const int64_t tiles = ((L + TR - 1) / TR) * a.segs;
+      if (tiles >= 2048 && (TR + 2) * (a.TW + 2) <= kTileLdsMaxWords) {
+        a.RPW = rpw;
+        break;
+      }
     }
   }
   const int64_t TR = 4 * (int64_t)a.R * a.RPW;

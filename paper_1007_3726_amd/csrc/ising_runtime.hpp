@@ -20,8 +20,11 @@ constexpr size_t kScratchBytes = 256 + 2 * (size_t)kMaxSweepBlocks * 16;
 struct Tuning {
   int64_t small_lds_bytes;  // lattices with both planes <= this run LDS-resident in one workgroup
   int max_blocks;           // grid cap of the grid-stride half-sweep kernels
+  int rpw;                  // row groups per wave in a tile (0: size rule)
 };
 
+// Shape for a lattice of side L: the autotuner's entry for L's size class
+// if one is installed, else the defaults.
 Tuning default_tuning(int64_t L);
 
 ising_status fail(ising_status code, const char* fmt, ...);
@@ -58,4 +61,5 @@ struct ising_lattice {
 namespace ising {
 ising::SweepArgs sweep_args(const ising_lattice* h, uint32_t t, int64_t* EM);
 ising_status enqueue_sweeps(ising_lattice* h, int64_t n, int64_t* dev_EM);
+bool tile_args(const ising_lattice* h, TileArgs* out);
 }  // namespace ising

@@ -43,6 +43,12 @@ class ising_request(ctypes.Structure):
                 ("spins_out", ctypes.POINTER(ctypes.c_int8))]
 
 
+class ising_tuning(ctypes.Structure):
+    _fields_ = [("L_min", ctypes.c_int64), ("L_max", ctypes.c_int64), ("rpw", ctypes.c_int32),
+                ("max_blocks", ctypes.c_int32), ("small_lds_bytes", ctypes.c_int64),
+                ("updates_per_ns", ctypes.c_double)]
+
+
 class ising_result(ctypes.Structure):
     _fields_ = [("ticket", ctypes.c_uint64), ("status", ctypes.c_int32),
                 ("E_final", ctypes.c_int64), ("M_final", ctypes.c_int64),
@@ -86,6 +92,10 @@ def lib():
         "ising_multi_sweep": ([P(vp), i32, i64, P(vp)], i32),
         "ising_multi_sweep_form": ([P(vp), i32, i64, P(vp), i32, i32], i32),
         "ising_batch_plan": ([P(i64), i32, i32, P(i32), P(i32), P(ctypes.c_double)], i32),
+        "ising_autotune": ([i64, vp, ctypes.c_size_t, vp, i32, P(ising_tuning)], i32),
+        "ising_tuning_set": ([P(ising_tuning), i32], i32),
+        "ising_tuning_get": ([P(ising_tuning), i32, P(i32)], i32),
+        "ising_tuning_clear": ([], i32),
         "ising_server_create": ([vp, ctypes.c_size_t, vp, i32, P(vp)], i32),
         "ising_batch_submit": ([vp, P(ising_request), i32, P(u64)], i32),
         "ising_server_step": ([vp], i32),
@@ -221,6 +231,56 @@ class Lattice:
         L, W, p = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_void_p()
         check(lib().ising_get_info(self.h, ctypes.byref(L), ctypes.byref(W), ctypes.byref(p)))
         return int(L.value), int(W.value), int(p.value or 0)
+
+
+_TUNING_KEYS = ["L_min", "L_max", "rpw", "max_blocks", "small_lds_bytes", "updates_per_ns"]
+
+
+def autotune(L: int, trial_sweeps: int = 10, device="cuda", stream=None) -> dict:
+    """Time the plain sweep's candidate shapes for side L and install the fastest
+    for L's size class; returns the chosen entry."""
+    import torch
+    dev = torch.device(device)
+    st = stream if stream is not None else torch.cuda.current_stream(dev)
+    nbytes = ising_lattice_bytes(L)
+    buf = _dev_alloc(nbytes, dev)
+    out = ising_tuning()
+    check(lib().ising_autotune(int(L), buf.data_ptr(), nbytes, _stream_ptr(st), int(trial_sweeps),
+                               ctypes.byref(out)))
+    return {k: getattr(out, k) for k in _TUNING_KEYS}
+
+
+def tuning_get():
+    """Installed tuning entries as a list of dicts."""
+    n = ctypes.c_int32()
+    check(lib().ising_tuning_get(None, 0, ctypes.byref(n)))
+    arr = (ising_tuning * max(n.value, 1))()
+    check(lib().ising_tuning_get(arr, n.value, ctypes.byref(n)))
+    return [{k: getattr(arr[i], k) for k in _TUNING_KEYS} for i in range(n.value)]
+
+
+def tuning_set(entries):
+    arr = (ising_tuning * max(len(entries), 1))()
+    for i, e in enumerate(entries):
+        for k in _TUNING_KEYS:
+            setattr(arr[i], k, e[k])
+    check(lib().ising_tuning_set(arr, len(entries)))
+
+
+def tuning_clear():
+    check(lib().ising_tuning_clear())
+
+
+def save_tuning(path: str):
+    import json
+    with open(path, "w") as f:
+        json.dump(tuning_get(), f, indent=1)
+
+
+def load_tuning(path: str):
+    import json
+    with open(path) as f:
+        tuning_set(json.load(f))
 
 
 def batch_plan(Ls: Sequence[int], cus: int = 256):

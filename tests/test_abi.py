@@ -75,3 +75,21 @@ def test_null_handles_are_rejected(L):
     assert L.ising_destroy(None) == 0
     E = ctypes.c_int64()
     assert L.ising_measure(None, ctypes.byref(E), ctypes.byref(E)) == -1
+
+
+def test_tuning_table_roundtrip(L):
+    from paper_1007_3726_amd import ising
+    ising.tuning_clear()
+    e = {"L_min": 8192, "L_max": 16383, "rpw": 2, "max_blocks": 1024, "small_lds_bytes": 0,
+         "updates_per_ns": 1.5}
+    ising.tuning_set([e])
+    assert ising.tuning_get() == [e]
+    e2 = dict(e, rpw=4)
+    ising.tuning_set([e2])  # same class replaces
+    assert ising.tuning_get() == [e2]
+    for bad in (dict(e, max_blocks=4096), dict(e, rpw=-1), dict(e, L_max=10),
+                dict(e, small_lds_bytes=1 << 20)):
+        with pytest.raises(ising.IsingError):
+            ising.tuning_set([bad])
+    ising.tuning_clear()
+    assert ising.tuning_get() == []
