@@ -15,9 +15,12 @@ Usage: python bench.py [--gpus 1] [--steps 3] [--warmup 1]
 """
 import argparse
 import json
+import math
 import os
 import sys
 import time
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -26,7 +29,7 @@ import workloads  # noqa: E402
 
 # VALU issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane-operations/s.
 VALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
-# Algorithmic lane-operations per spin update (derivation in the design doc):
+# Algorithmic lane-operations per spin update:
 # a quarter of a Philox4x32-10 block (10 rounds x (2 wide multiplies + 2
 # three-input XORs) / 4 = 10), two threshold compares and two bit inserts.
 ALU_OPS_PER_UPDATE = 14.0
@@ -233,6 +236,7 @@ def bench_batched(torch, ising, dev, sweeps):
     dt_plain = time.perf_counter() - t1
     plain_updates = sum(g.L * g.L for g in grid) * plain_sweeps
     tidx = [0, len(workloads.FSS_TEMPS) // 2, len(workloads.FSS_TEMPS) - 1]
+    fss = bench_fss(torch, ising, dev, grid, EMs, discard)
     return {
         "value": round(updates / (dt * 1e9), 2), "unit": "spin updates/ns",
         "workload": "224 lattices, L in {64..4096} x 32 T in [2.20, 2.34], hot start, "
@@ -243,7 +247,85 @@ def bench_batched(torch, ising, dev, sweeps):
         "binder_U4": {str(L): {"%.4f" % workloads.FSS_TEMPS[i]: round(v[i], 4) for i in tidx}
                       for L, v in binder.items()},
         "discard": discard,
+        "fss": fss,
     }
+
+
+def bench_fss(torch, ising, dev, grid, EMs, discard, per_interval=8, nblocks=20):
+    """Binder-cumulant crossings of adjacent sizes of the batched grid: the
+    series are reweighted on the device to a grid 8x finer than the simulated
+    temperatures (each point from the nearest run), with jackknife errors."""
+    temps = np.array([g.T for g in grid])
+    Ls = [g.L for g in grid]
+    T_lo, T_hi = float(temps.min()), float(temps.max())
+    n_sim = len(workloads.FSS_TEMPS)
+    fine = np.linspace(T_lo, T_hi, (n_sim - 1) * per_interval + 1)
+    stream = torch.cuda.current_stream(dev)
+    # time the reweighting kernel alone on the stream it runs on
+    tl, tb = [], []
+    for L in sorted(set(Ls)):
+        runs = [i for i, v in enumerate(Ls) if v == L]
+        for T in fine:
+            tl.append(runs[int(np.argmin(np.abs(temps[runs] - T)))])
+            tb.append(1.0 / T)
+    ising.reweight(EMs, [1.0 / t for t in temps], [discard] * len(EMs), tl, tb, nblocks, stream)
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    ising.reweight(EMs, [1.0 / t for t in temps], [discard] * len(EMs), tl, tb, nblocks, stream)
+    b.record(stream)
+    b.synchronize()
+    rw_ms = a.elapsed_time(b)
+    t0 = time.perf_counter()
+    curves = ising.binder_curves(EMs, Ls, temps, discard, fine, nblocks, stream)
+    sizes = sorted(curves)
+    cross = {}
+    for x, y in zip(sizes[:-1], sizes[1:]):
+        t, u, et, eu = ising.binder_crossing(fine, curves[x][0][:, 0], curves[y][0][:, 0],
+                                             curves[x][2], curves[y][2])
+        cross["%d/%d" % (x, y)] = {"T": round(t, 5), "T_err": round(et, 5), "U4": round(u, 4),
+                                   "U4_err": round(eu, 4)}
+    chain_s = time.perf_counter() - t0
+    samples = EMs[0].shape[0] - discard
+    return {"grid_points": len(fine), "tasks": len(tl), "samples_per_task": int(samples),
+            "nblocks": nblocks, "reweight_ms": round(rw_ms, 3),
+            "reweight_samples_per_s": round(len(tl) * samples / (rw_ms * 1e-3), 1),
+            "analysis_s": round(chain_s, 3), "crossings": cross,
+            "tc_exact": round(2.0 / math.log(1.0 + math.sqrt(2.0)), 6)}
+
+
+def bench_fss_proof(torch, ising, dev, sweeps=200_000, discard=20_000, nblocks=20):
+    """The paper's proof of concept (section 2): Binder cumulants of small
+    lattices (L = 8..64, six temperatures in [2.15, 2.40], long runs on the
+    batched path) cross near T_C."""
+    temps = np.linspace(2.15, 2.40, 6)
+    sizes = (8, 16, 32, 64)
+    lats, EMs, Ls, T_all = [], [], [], []
+    for L in sizes:
+        for i, T in enumerate(temps):
+            lats.append(ising.Lattice(L, seed=7 + i, stream_id=L, init=workloads.INIT_HOT,
+                                      beta=1.0 / T, device=dev))
+            EMs.append(torch.empty((sweeps, 2), dtype=torch.int64, device=dev))
+            Ls.append(L)
+            T_all.append(T)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ising.multi_sweep(lats, sweeps, EMs)
+    dt = time.perf_counter() - t0
+    fine = np.linspace(2.15, 2.40, 51)
+    curves = ising.binder_curves(EMs, Ls, T_all, discard, fine, nblocks)
+    cross = {}
+    for x, y in zip(sizes[:-1], sizes[1:]):
+        t, u, et, eu = ising.binder_crossing(fine, curves[x][0][:, 0], curves[y][0][:, 0],
+                                             curves[x][2], curves[y][2])
+        cross["%d/%d" % (x, y)] = {"T": round(t, 5), "T_err": round(et, 5), "U4": round(u, 4),
+                                   "U4_err": round(eu, 4)}
+    return {"workload": "L in {8,16,32,64} x 6 T in [2.15, 2.40], hot start, %d sweeps, "
+                        "discard %d" % (sweeps, discard),
+            "seconds": round(dt, 3),
+            "updates_per_ns": round(sum(L * L for L in Ls) * sweeps / (dt * 1e9), 2),
+            "crossings": cross,
+            "tc_exact": round(2.0 / math.log(1.0 + math.sqrt(2.0)), 6)}
 
 
 def cpu_baseline(w, sweeps):
@@ -356,6 +438,9 @@ def main():
               flush=True)
         del EM
         result["batched"] = bench_batched(torch, ising, dev, args.batched_sweeps)
+        print("bench: FSS proof of concept (small lattices, long runs)", file=sys.stderr,
+              flush=True)
+        result["fss_proof"] = bench_fss_proof(torch, ising, dev)
     if not args.no_served:
         print("bench: served stream (%d requests)" % args.served_requests, file=sys.stderr,
               flush=True)

@@ -226,6 +226,62 @@ ISING_API ising_status ising_tuning_lookup(int64_t L, ising_tuning *out);
 ISING_API ising_status ising_tuning_clear(void);
 
 /* ---------------------------------------------------------------- */
+/* Finite-size-scaling analysis of per-sweep (E, M) series.           */
+/* ---------------------------------------------------------------- */
+
+/*
+ * Single-histogram reweighting (Ferrenberg and Swendsen, PRL 61, 2635
+ * (1988)) of device-resident per-sweep series, the input of the Binder
+ * cumulant crossing by which the paper locates T_C (section 2, Eq. (2)).
+ *
+ * Series i is n_sweeps[i] rows of int64 (E, M) at dev_EM[i] (device, as
+ * written by ising_sweep / ising_multi_sweep), simulated at beta0[i]
+ * (finite, >= 0).  Sweeps discard[i] .. n_sweeps[i]-1 are kept (at least
+ * nblocks of them); kept sweep j belongs to block floor(j * nblocks / count).
+ * Task k reweights series task_lattice[k] to task_beta[k] (finite, >= 0):
+ * with x_t = -(beta - beta0)(E_t - E_ref), E_ref = E of the first kept sweep,
+ * and w_t = exp(x_t - max x), it writes for every block b the five fp64
+ * sums  w, w|M|, w M^2, w M^4, w E  to dev_sums[(k * nblocks + b) * 5 + i]
+ * (device, ntask * nblocks * 5 doubles, caller-owned) and max x to
+ * dev_shift[k] (device, may be NULL).  1 <= nblocks <= 4096.  The host
+ * arrays are read before the call returns; the library copies them to a
+ * device table it owns and waits for the stream before the launch; the
+ * kernel runs asynchronously on hip_stream.
+ */
+ISING_API ising_status ising_reweight(int32_t nlat, const int64_t *const *dev_EM,
+                                      const int64_t *n_sweeps, const int64_t *discard,
+                                      const double *beta0, int32_t ntask,
+                                      const int32_t *task_lattice, const double *task_beta,
+                                      int32_t nblocks, double *dev_sums, double *dev_shift,
+                                      void *hip_stream);
+
+/*
+ * From the per-block sums of ising_reweight (host copy, ntask * nblocks * 5
+ * doubles) and the number of sites N of each task's lattice: est[3k..3k+2] =
+ * (U4, <E>/N, <|M|>/N) of the totals, U4 = 1 - <M^4> / (3 <M^2>^2) (Eq. (2)),
+ * err[3k..] their delete-one-block jackknife errors
+ * sqrt((B-1)/B sum_b (q_b - mean q)^2), and, if u4_rep is not NULL,
+ * u4_rep[k * nblocks + b] = U4 without block b.  nblocks >= 2.  Host only.
+ */
+ISING_API ising_status ising_fss_moments(const double *sums, int32_t ntask, int32_t nblocks,
+                                         const int64_t *sites, double *est, double *err,
+                                         double *u4_rep);
+
+/*
+ * Crossing of two Binder-cumulant curves on an ascending grid T[0..K-1]: Ua
+ * of the smaller lattice, Ub of the larger.  With d = Ua - Ub, the first k
+ * with d[k] < 0 <= d[k+1] gives T* by linear interpolation and U* = Ua at
+ * T* (below T_C the larger lattice has the larger U4).  out[0..3] = T*, U*,
+ * and their jackknife errors from the replica curves Ua_rep / Ub_rep
+ * (nblocks x K each, may both be NULL).  NaN where there is no such k (in
+ * the full curves, or in any replica for the errors).  Host only.
+ */
+ISING_API ising_status ising_binder_crossing(const double *T, int32_t K, const double *Ua,
+                                             const double *Ub, const double *Ua_rep,
+                                             const double *Ub_rep, int32_t nblocks,
+                                             double *out);
+
+/* ---------------------------------------------------------------- */
 /* Served mode: continuous batching of independent simulations.      */
 /* ---------------------------------------------------------------- */
 

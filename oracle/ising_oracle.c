@@ -21,7 +21,7 @@
  *     the factor is the integer threshold floor(exp(-dH/T) * 2^32), clamped
  *     to 2^32 - 1, so "r < exp(-dH/T)" becomes "u < threshold".
  *
- * Readings of points the paper leaves open (listed in the design doc):
+ * Readings of points the paper leaves open:
  *   - colour of site (x, y) is (x + y) mod 2; colour 0 is updated first;
  *   - the uniforms come from Philox4x32-10 (Salmon, Moraes, Dror, Shaw,
  *     "Parallel random numbers: as easy as 1, 2, 3", SC'11), keyed by

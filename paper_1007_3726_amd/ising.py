@@ -107,6 +107,10 @@ def lib():
         "ising_server_inject_fault": ([vp, i64], i32),
         "ising_server_stats": ([vp, P(i64)], i32),
         "ising_server_destroy": ([vp], i32),
+        "ising_reweight": ([i32, P(vp), P(i64), P(i64), P(ctypes.c_double), i32, P(i32),
+                            P(ctypes.c_double), i32, vp, vp, vp], i32),
+        "ising_fss_moments": ([vp, i32, i32, P(i64), vp, vp, vp], i32),
+        "ising_binder_crossing": ([vp, i32, vp, vp, vp, vp, i32, vp], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -315,6 +319,93 @@ def multi_sweep(lattices: Sequence[Lattice], n: int, EMs=None, form=None, graph_
             *[(e.data_ptr() if e is not None else None) for e in EMs])
     f = {None: -1, "fused": 0, "packed": 1}[form]
     check(lib().ising_multi_sweep_form(arr, len(lattices), int(n), em_arr, f, int(graph_chunk)))
+
+
+def reweight(EMs, betas0, discards, task_lattice, task_beta, nblocks: int, stream=None):
+    """Per-block reweighted sums of device series (ising_reweight).
+
+    EMs: int64 (n, 2) device tensors; betas0, discards: one per series;
+    tasks: task_lattice[k] (series index) reweighted to task_beta[k].
+    Returns (sums, shift): float64 device tensors (ntask, nblocks, 5), (ntask,)."""
+    import torch
+    nl, nt = len(EMs), len(task_lattice)
+    dev = EMs[0].device
+    st = stream if stream is not None else torch.cuda.current_stream(dev)
+    for e in EMs:
+        if e.dtype != torch.int64 or e.dim() != 2 or e.shape[1] != 2 or not e.is_contiguous():
+            raise IsingError(ISING_EINVAL, "reweight: series must be contiguous int64 (n, 2)")
+    sums = torch.empty((max(nt, 1), nblocks, 5), dtype=torch.float64, device=dev)
+    shift = torch.empty((max(nt, 1),), dtype=torch.float64, device=dev)
+    ptrs = (ctypes.c_void_p * max(nl, 1))(*[e.data_ptr() for e in EMs])
+    n = (ctypes.c_int64 * max(nl, 1))(*[int(e.shape[0]) for e in EMs])
+    d = (ctypes.c_int64 * max(nl, 1))(*[int(v) for v in discards])
+    b0 = (ctypes.c_double * max(nl, 1))(*[float(v) for v in betas0])
+    tl = (ctypes.c_int32 * max(nt, 1))(*[int(v) for v in task_lattice])
+    tb = (ctypes.c_double * max(nt, 1))(*[float(v) for v in task_beta])
+    check(lib().ising_reweight(nl, ptrs, n, d, b0, nt, tl, tb, int(nblocks), sums.data_ptr(),
+                               shift.data_ptr(), _stream_ptr(st)))
+    return sums, shift
+
+
+def fss_moments(sums, sites):
+    """(est, err, u4_rep) from host per-block sums (ntask, B, 5) (ising_fss_moments):
+    est/err (ntask, 3) = (U4, <E>/N, <|M|>/N) and jackknife errors, u4_rep (ntask, B)."""
+    import numpy as np
+    S = np.ascontiguousarray(np.asarray(sums, dtype=np.float64))
+    nt, B = S.shape[0], S.shape[1]
+    N = np.ascontiguousarray(np.asarray(sites, dtype=np.int64).reshape(nt))
+    est = np.empty((nt, 3))
+    err = np.empty((nt, 3))
+    rep = np.empty((nt, B))
+    check(lib().ising_fss_moments(S.ctypes.data, nt, B,
+                                  N.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                  est.ctypes.data, err.ctypes.data, rep.ctypes.data))
+    return est, err, rep
+
+
+def binder_crossing(T, Ua, Ub, Ua_rep=None, Ub_rep=None):
+    """(T*, U*, err T*, err U*) of two U4 curves (ising_binder_crossing)."""
+    import numpy as np
+    T = np.ascontiguousarray(T, dtype=np.float64)
+    a = np.ascontiguousarray(Ua, dtype=np.float64)
+    b = np.ascontiguousarray(Ub, dtype=np.float64)
+    out = np.empty(4)
+    ra = rb = None
+    B = 0
+    if Ua_rep is not None:
+        ra = np.ascontiguousarray(Ua_rep, dtype=np.float64)
+        rb = np.ascontiguousarray(Ub_rep, dtype=np.float64)
+        B = ra.shape[0]
+    check(lib().ising_binder_crossing(T.ctypes.data, len(T), a.ctypes.data, b.ctypes.data,
+                                      None if ra is None else ra.ctypes.data,
+                                      None if rb is None else rb.ctypes.data, B,
+                                      out.ctypes.data))
+    return tuple(float(v) for v in out)
+
+
+def binder_curves(EMs, Ls, temps, discard: int, T_grid, nblocks: int = 20, stream=None):
+    """U4 curves on T_grid for every lattice size among Ls: each grid point is
+    reweighted from the run of that size whose temperature is nearest.
+    Returns {L: (est (K, 3), err (K, 3), u4_rep (nblocks, K))}."""
+    import numpy as np
+    Ls = [int(v) for v in Ls]
+    temps = np.asarray(temps, dtype=np.float64)
+    T_grid = np.asarray(T_grid, dtype=np.float64)
+    sizes = sorted(set(Ls))
+    tl, tb, tsite = [], [], []
+    for L in sizes:
+        runs = [i for i, v in enumerate(Ls) if v == L]
+        for T in T_grid:
+            i = runs[int(np.argmin(np.abs(temps[runs] - T)))]
+            tl.append(i)
+            tb.append(1.0 / T)
+            tsite.append(L * L)
+    sums, _ = reweight(EMs, [1.0 / t for t in temps], [discard] * len(EMs), tl, tb, nblocks,
+                       stream)
+    est, err, rep = fss_moments(sums.cpu().numpy(), tsite)
+    K = len(T_grid)
+    return {L: (est[j * K:(j + 1) * K], err[j * K:(j + 1) * K], rep[j * K:(j + 1) * K].T.copy())
+            for j, L in enumerate(sizes)}
 
 
 class Server:
