@@ -181,7 +181,8 @@ ISING_API ising_status ising_batch_plan(const int64_t *Ls, int32_t count, int32_
 /* Autotuner: launch shapes of the plain sweep per lattice size class. */
 /* ---------------------------------------------------------------- */
 
-#define ISING_FORM_TILE 0  /* workgroup tiles, other colour's rows staged in LDS */
+#define ISING_FORM_TILE 0  /* workgroup tiles of 4 independent waves, neighbour words
+                              loaded directly (the default) */
 #define ISING_FORM_STRIP 1 /* one wave per 64-word x rpw-row strip, rows rolled in
                               registers (rows of >= 63 words only; others use tiles) */
 

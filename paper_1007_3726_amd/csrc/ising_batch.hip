@@ -137,7 +137,8 @@ static ising_status run_fused(ising_lattice* const* hs, const std::vector<int>& 
   const size_t off_lat = 256;
   const size_t off_tiles = align_up(off_lat + nl * sizeof(FusedLattice), 256);
   const size_t off_part = align_up(off_tiles + ntiles * sizeof(FusedTile), 256);
-  const size_t bytes = align_up(off_part + 2 * 2 * (size_t)ntiles * sizeof(uint32_t), 256);
+  // per-wave E/M partials: 2 sweep slots x 4 waves x (anti, up) per tile
+  const size_t bytes = align_up(off_part + 2 * 4 * 2 * (size_t)ntiles * sizeof(uint32_t), 256);
   ising_status st = ensure_table(T, bytes);
   if (st != ISING_OK) return st;
   char* d = (char*)T.ptr;

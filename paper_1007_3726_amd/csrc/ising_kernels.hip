@@ -226,10 +226,14 @@ __global__ __launch_bounds__(1024) void k_small_sweeps(SmallArgs a) {
 // Work unit: a tile of TR = 4*R*RPW rows x TW words of colour C.  A wave
 // processes RPW row groups of the tile one after the other, one word per
 // lane per group (W >= kWideMinWords: a row group is one row of a 64-word segment;
-// W < 64: a row group is R = floor(64/W) whole rows).  The other colour's
-// rows y0-1 .. y0+TR and words w0-1 .. w0+TW (periodic) are staged in LDS
-// with coalesced loads, so each neighbour word is read from HBM/L2 about
-// once per tile instead of three times.  The Philox block index of word
+// W < 64: a row group is R = floor(64/W) whole rows).  The plain and fused
+// kernels read each word's four neighbour words directly
+// (process_tile_direct: the rows that neighbouring lanes and tiles share
+// hit in L1/L2, the loads are issued before the Philox stretch and used
+// after it, and the waves of a workgroup never wait for each other).  The
+// packed persistent kernel stages the other colour's rows y0-1 .. y0+TR
+// and words w0-1 .. w0+TW (periodic) in LDS instead (process_tile), since
+// it needs block barriers between colour steps anyway.  The Philox block index of word
 // (y, w) is y*L/8 + 16*w + q; its high word is 0 (hi_mode 0) or uniform
 // over the wave's row (hi_mode 1), so only the low word varies per lane.
 //
@@ -393,21 +397,77 @@ __device__ __forceinline__ void process_tile(const TileArgs& a, const TileLane& 
   __syncthreads();
 }
 
-// One colour step of one lattice over the tiles first, first + stride, ...
-// of the tiled layout described above.  `colour` and `em` are uniform; the
-// callers pass constants where they can.  Ends with a block barrier.
+// The same tile of one colour step without LDS staging: each lane loads its
+// own word and its four neighbour words straight from memory (the rows
+// shared by neighbouring lanes hit in L1/L2), issues the loads before the
+// Philox stretch and uses them after it.  No block barrier: the four waves
+// of a workgroup work independently.
 template <bool FULL, int WIDEM, bool BUMP_SALU = false>
-__device__ __forceinline__ void sweep_tiles(const TileArgs& a, int colour, bool em,
-                                            int64_t first, int64_t stride, uint64_t* tile,
-                                            uint32_t& anti, uint32_t& up) {
-  const TileLane tl = tile_lane<WIDEM>(a);
-  for (int64_t tidx = first; tidx < a.tiles; tidx += stride)
-    process_tile<FULL, WIDEM, BUMP_SALU>(a, tl, colour, em, tidx, tile, anti, up);
+__device__ __forceinline__ void process_tile_direct(const TileArgs& a, const TileLane& tl,
+                                                    int colour, bool em, int64_t tidx,
+                                                    uint32_t& anti, uint32_t& up) {
+  const Geom& g = a.g;
+  const bool WIDE = WIDEM == 2 ? tl.wide : (WIDEM == 1);
+  uint64_t* __restrict__ self = a.planes + (colour ? a.plane_words : 0);
+  const uint64_t* __restrict__ other = a.planes + (colour ? 0 : a.plane_words);
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int R = a.R, RPW = a.RPW;
+  const uint32_t ctr3 = a.sid4 | (uint32_t)colour;
+  const int64_t y0 = (tidx / a.segs) * tl.TR;
+  const int32_t w0 = WIDE ? (int32_t)(tidx % a.segs) * 64 : 0;
+  const int64_t W = g.W;
+  for (int j = 0; j < RPW; ++j) {
+    const int r_l = (wave * RPW + j) * R + tl.r_off;
+    const int64_t y = y0 + r_l;
+    const int32_t w = w0 + tl.w_l;
+    if (!(tl.lane_ok && y < g.L && w < W)) continue;
+    const int64_t ym = y == 0 ? g.L - 1 : y - 1;
+    const int64_t yp = y == g.L - 1 ? 0 : y + 1;
+    // horizontal partner: left (site k-1) when (y + colour) is even, else right
+    const bool left = ((y + colour) & 1) == 0;
+    const int32_t ws = left ? (w > 0 ? w - 1 : (int32_t)W - 1) : (w < W - 1 ? w + 1 : 0);
+    const uint64_t s = self[y * W + w];
+    const uint64_t n0 = other[y * W + w];
+    const uint64_t n2 = other[ym * W + w];
+    const uint64_t n3 = other[yp * W + w];
+    const uint64_t sd = other[y * W + ws];
+    uint32_t lo, hi;
+    if (a.hi_mode == 0) {
+      lo = (uint32_t)y * (uint32_t)g.L8 + 16u * (uint32_t)w;
+      hi = 0;
+    } else {
+      const uint64_t gy =
+          (uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)y) * (uint64_t)g.L8;
+      hi = (uint32_t)(gy >> 32);
+      lo = (uint32_t)gy + 16u * (uint32_t)w;
+    }
+    const int nq = (FULL || w < W - 1) ? 16 : (g.nb_last >> 2);
+    uint64_t r4, r8;
+    masks_shift<FULL, BUMP_SALU>(lo, hi, nq, a.k0, a.k1, a.t, ctr3, a.t4, a.t8, r4, r8);
+    __builtin_amdgcn_sched_barrier(0);
+    Nbr n;
+    n.n0 = n0;
+    n.n2 = n2;
+    n.n3 = n3;
+    if (FULL) {
+      n.n1 = left ? ((n0 << 1) | (sd >> 63)) : ((n0 >> 1) | (sd << 63));
+    } else {
+      const uint64_t bl = w > 0 ? (sd >> 63) : ((sd >> (g.nb_last - 1)) & 1ull);
+      const uint64_t br = w < W - 1 ? (sd << 63) : ((sd & 1ull) << (g.nb_last - 1));
+      n.n1 = left ? ((n0 << 1) | bl) : ((n0 >> 1) | br);
+    }
+    const uint64_t valid = (FULL || w < W - 1) ? ~0ull : low_mask(g.nb_last);
+    const uint64_t s_new = s ^ (flip_mask(s, n, r4, r8) & valid);
+    self[y * W + w] = s_new;
+    if (colour == 1 && em) count_word(s_new, n, valid, anti, up);
+  }
 }
 
+// Tiles read their neighbour words directly (process_tile_direct): no LDS
+// staging and no barrier until the E/M reduction at the end.
 template <int C, bool EM, bool FULL, bool WIDE>
-__global__ __launch_bounds__(256) void k_tile_sweep(TileArgs a) {
-  __shared__ uint64_t tile[kTileLdsMaxWords];
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_tile_sweep(
+    TileArgs a) {
   __shared__ uint64_t red64[8];
   __shared__ uint32_t red[8];
   if (C == 0 && a.prev_EM != nullptr && blockIdx.x == 0)
@@ -417,7 +477,9 @@ __global__ __launch_bounds__(256) void k_tile_sweep(TileArgs a) {
   const int b = blockIdx.x;
   const int lb = (G % 8 == 0) ? (b % 8) * (G / 8) + b / 8 : b;
   uint32_t anti = 0, up = 0;
-  sweep_tiles<FULL, WIDE ? 1 : 0>(a, C, EM, lb, G, tile, anti, up);
+  const TileLane tl = tile_lane<WIDE ? 1 : 0>(a);
+  for (int64_t tidx = lb; tidx < a.tiles; tidx += G)
+    process_tile_direct<FULL, WIDE ? 1 : 0>(a, tl, C, EM, tidx, anti, up);
   if (C == 1 && EM) {
     block_sum2(anti, up, red);
     if (threadIdx.x == 0) {
@@ -573,18 +635,35 @@ __global__ __launch_bounds__(256) void k_finalize_em(const uint64_t* part, int n
 // one workgroup: every workgroup runs its packed list of lattices for all
 // n sweeps with block barriers only (one launch in total).
 // ---------------------------------------------------------------------
-__device__ __forceinline__ void finalize_tiles(const FusedArgs& f, uint32_t k, uint32_t* red) {
-  const uint32_t* part = f.part + (size_t)(k & 1u) * 2 * f.ntiles;
+__device__ __forceinline__ void finalize_tiles(const FusedArgs& f, uint32_t k, uint64_t* red64) {
+  // per-wave partials: 4 slots of (anti, up) per tile; lattice totals need
+  // 64 bits (2 N reaches 2^32 at L = 46341)
+  const uint32_t* part = f.part + (size_t)(k & 1u) * 8 * f.ntiles;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int l = blockIdx.x; l < f.nlat; l += gridDim.x) {
     const FusedLattice Lt = ((const FusedLattice ISING_CONSTANT_AS*)f.lat)[l];
     if (Lt.EM == nullptr || (int64_t)k >= Lt.nsweeps) continue;
-    uint32_t a = 0, p = 0;
-    for (int64_t i = threadIdx.x; i < Lt.ntiles; i += blockDim.x) {
-      a += part[2 * (Lt.first_tile + i)];
-      p += part[2 * (Lt.first_tile + i) + 1];
+    uint64_t a = 0, p = 0;
+    for (int64_t i = threadIdx.x; i < 4 * Lt.ntiles; i += blockDim.x) {
+      a += part[2 * (4 * Lt.first_tile + i)];
+      p += part[2 * (4 * Lt.first_tile + i) + 1];
     }
-    block_sum2(a, p, red);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      a += __shfl_xor(a, off, 64);
+      p += __shfl_xor(p, off, 64);
+    }
+    if (lane == 0) {
+      red64[2 * wave] = a;
+      red64[2 * wave + 1] = p;
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
+      a = p = 0;
+      for (int i = 0; i < (int)(blockDim.x >> 6); ++i) {
+        a += red64[2 * i];
+        p += red64[2 * i + 1];
+      }
       const int64_t L = Lt.ta.g.L;
       Lt.EM[2 * (int64_t)k] = 2 * (int64_t)a - 2 * L * L;
       Lt.EM[2 * (int64_t)k + 1] = 2 * (int64_t)p - L * L;
@@ -593,16 +672,18 @@ __device__ __forceinline__ void finalize_tiles(const FusedArgs& f, uint32_t k, u
   }
 }
 
+// 8 waves per SIMD need <= 100 SGPRs (the grid assumes 8 workgroups per CU)
 template <int C>
-__global__ __launch_bounds__(256) void k_fused(FusedArgs f) {
-  __shared__ uint64_t tile[kTileLdsMaxWords];
-  __shared__ uint32_t red[8];
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_fused(
+    FusedArgs f) {
+  __shared__ uint64_t red64[8];
   const uint32_t k = *((const uint32_t ISING_CONSTANT_AS*)f.kbase) + (uint32_t)f.klocal;
-  if (C == 0 && k > 0) finalize_tiles(f, k - 1, red);
+  if (C == 0 && k > 0) finalize_tiles(f, k - 1, red64);
   const int G = gridDim.x;
   const int b = blockIdx.x;
   const int lb = (G % 8 == 0) ? (b % 8) * (G / 8) + b / 8 : b;
-  uint32_t* part = f.part + (size_t)(k & 1u) * 2 * f.ntiles;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  uint32_t* part = f.part + (size_t)(k & 1u) * 8 * f.ntiles;
   for (int64_t tidx = lb; tidx < f.ntiles; tidx += G) {
     const FusedTile ft = ((const FusedTile ISING_CONSTANT_AS*)f.tiles)[tidx];
     const FusedLattice Lt = ((const FusedLattice ISING_CONSTANT_AS*)f.lat)[ft.lattice];
@@ -613,23 +694,24 @@ __global__ __launch_bounds__(256) void k_fused(FusedArgs f) {
     const TileLane tl = tile_lane<2>(a);
     uint32_t anti = 0, up = 0;
     if (a.g.nb_last == 64)
-      process_tile<true, 2, true>(a, tl, C, em, ft.local, tile, anti, up);
+      process_tile_direct<true, 2, true>(a, tl, C, em, ft.local, anti, up);
     else
-      process_tile<false, 2, true>(a, tl, C, em, ft.local, tile, anti, up);
+      process_tile_direct<false, 2, true>(a, tl, C, em, ft.local, anti, up);
     if (em) {
-      block_sum2(anti, up, red);
-      if (threadIdx.x == 0) {
-        part[2 * tidx] = anti;
-        part[2 * tidx + 1] = up;
+      anti = wave_sum(anti);
+      up = wave_sum(up);
+      if ((threadIdx.x & 63) == 0) {
+        part[2 * (4 * tidx + wave)] = anti;
+        part[2 * (4 * tidx + wave) + 1] = up;
       }
     }
   }
 }
 
 __global__ __launch_bounds__(256) void k_fused_finalize(FusedArgs f) {
-  __shared__ uint32_t red[8];
+  __shared__ uint64_t red64[8];
   const uint32_t k = *((const uint32_t ISING_CONSTANT_AS*)f.kbase) + (uint32_t)f.klocal;
-  finalize_tiles(f, k, red);
+  finalize_tiles(f, k, red64);
 }
 
 __global__ void k_advance(uint32_t* kbase, uint32_t by) {

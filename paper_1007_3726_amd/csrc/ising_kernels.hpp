@@ -29,8 +29,9 @@ struct SmallArgs {
 };
 
 // Tiled half-sweep (L % 8 == 0): a workgroup of four waves handles a tile
-// of 4*R rows x TW words of one colour; the neighbour rows of the other
-// colour are staged in LDS once per tile.
+// of 4*R*RPW rows x TW words of one colour (the packed persistent kernel
+// stages the neighbour rows of the other colour in LDS once per tile, and
+// the tile shape is bounded by that staging area).
 constexpr int kTileLdsMaxWords = 2048;
 // Rows of at least this many words use the wide tile shape (64-word row
 // segments).  A narrow tile stages whole rows of W + 2 words, and each such

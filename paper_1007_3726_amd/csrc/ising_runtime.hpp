@@ -21,7 +21,7 @@ struct Tuning {
   int64_t small_lds_bytes;  // lattices with both planes <= this run LDS-resident in one workgroup
   int max_blocks;           // grid cap of the grid-stride half-sweep kernels
   int rpw;                  // tile: row groups per wave; strip: rows per wave task (0: size rule)
-  int form;                 // 0: LDS-staged tiles, 1: register-rolled strips (wide rows only)
+  int form;                 // 0: tiles (default), 1: register-rolled strips (wide rows only)
 };
 
 // Shape for a lattice of side L: the autotuner's entry for L's size class

@@ -33,9 +33,9 @@ Tuning default_tuning(int64_t L) {
   t.small_lds_bytes = 4096;  // L <= 128 runs in one LDS-resident workgroup
   t.max_blocks = 2048;
   t.rpw = 0;
-  // rows of >= 63 words (L >= 7938) run as strips: measured 2-6 % faster than
-  // tiles from 8192^2 to 262144^2
-  t.form = (L / 2 + 63) / 64 >= kWideMinWords ? ISING_FORM_STRIP : ISING_FORM_TILE;
+  // tiles with direct neighbour loads: measured faster than strips at every
+  // size from 1024^2 to 262144^2 (strips stay an autotuner candidate)
+  t.form = ISING_FORM_TILE;
   std::lock_guard<std::mutex> lock(g_tune_mutex);
   for (const ising_tuning& e : g_table)
     if (L >= e.L_min && L <= e.L_max) {

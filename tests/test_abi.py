@@ -97,11 +97,10 @@ def test_tuning_table_roundtrip(L):
             ising.tuning_set([bad])
     ising.tuning_clear()
     assert ising.tuning_get() == []
-    # built-in defaults: LDS-resident up to 128^2, tiles for narrow rows,
-    # strips for rows of >= 63 words
+    # built-in defaults: LDS-resident up to 128^2, tiles above
     assert ising.tuning_lookup(64)["small_lds_bytes"] >= 2 * 64 * 8
     assert ising.tuning_lookup(4096)["form"] == ising.ISING_FORM_TILE
-    assert ising.tuning_lookup(8000)["form"] == ising.ISING_FORM_STRIP
+    assert ising.tuning_lookup(16384)["form"] == ising.ISING_FORM_TILE
     ising.tuning_set([e2])
     assert ising.tuning_lookup(9000)["rpw"] == 4 and ising.tuning_lookup(9000)["L_min"] == 8192
     ising.tuning_clear()
