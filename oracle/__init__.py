@@ -45,6 +45,13 @@ def lib():
         L.oracle_sweeps.restype = None
         L.oracle_window.argtypes = [i64, u32, u32, u64, u32, i32, u32, i64, i64, i64, i64, i64, p8]
         L.oracle_window.restype = i32
+        pu32w = ctypes.POINTER(ctypes.c_uint32)
+        L.oracle_lcg_threshold.argtypes = [ctypes.c_double, i32]
+        L.oracle_lcg_threshold.restype = u32
+        L.oracle_lcg_seed.argtypes = [i64, u64, pu32w]
+        L.oracle_lcg_seed.restype = None
+        L.oracle_lcg_sweeps.argtypes = [i64, u32, u32, i64, p8, pu32w, p64]
+        L.oracle_lcg_sweeps.restype = None
         L.oracle_get_threads.argtypes = []
         L.oracle_get_threads.restype = i32
         L.oracle_set_threads.argtypes = [i32]
@@ -129,6 +136,33 @@ def window(L, beta, seed, stream_id, init_kind, t0, n, x0, y0, w, h) -> np.ndarr
     if rc != 0:
         raise ValueError("window plus light-cone margin does not fit in the lattice")
     return out
+
+
+def lcg_thresholds(beta: float):
+    """(t4', t8') of the per-thread LCG dynamics: min(floor(exp(-beta dE) 2^31), 2^31)."""
+    check_beta(beta)
+    return (int(lib().oracle_lcg_threshold(beta, 4)), int(lib().oracle_lcg_threshold(beta, 8)))
+
+
+def lcg_seed(L: int, seed: int) -> np.ndarray:
+    """Thread seeds of Eq. (7): uint32 array (2, L, W), state[c, y, w]."""
+    W = (L // 2 + 63) // 64
+    st = np.empty((2, L, W), dtype=np.uint32)
+    lib().oracle_lcg_seed(L, seed, st.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)))
+    return st
+
+
+def lcg_sweeps(s: np.ndarray, beta: float, state: np.ndarray, n: int, record: bool = True):
+    """n sweeps of the per-thread-LCG dynamics in place (spins and states);
+    returns EM[n, 2] (or None)."""
+    L = s.shape[0]
+    assert s.dtype == np.int8 and s.flags.c_contiguous
+    assert state.dtype == np.uint32 and state.flags.c_contiguous
+    t4, t8 = lcg_thresholds(beta)
+    EM = np.empty((n, 2), dtype=np.int64) if record else None
+    lib().oracle_lcg_sweeps(L, t4, t8, n, _p8(s), state.ctypes.data_as(
+        ctypes.POINTER(ctypes.c_uint32)), _p64(EM) if record else None)
+    return EM
 
 
 def set_threads(n: int) -> None:

@@ -222,6 +222,88 @@ void oracle_sweeps(int64_t L, uint32_t t4, uint32_t t8, uint64_t seed, uint32_t 
     }
 }
 
+/* ================================================================== */
+/* The paper's own random numbers (section 5.3), as an alternative     */
+/* dynamics: one linear congruential generator per update thread,      */
+/*   x_{i+1} = (1664525 x_i + 1013904223) mod 2^32            (Eq. (6)) */
+/* normalised as y = |x / 2^31| with x read as a signed 32-bit integer, */
+/* and thread seeds x_{0,j+1} = 16807 x_{0,j} mod 2^32       (Eq. (7)). */
+/* Readings (the paper leaves the thread layout to its CUDA code):      */
+/*   - a "thread" is one 64-site word of one colour: word w of row y of */
+/*     colour c is thread j = (c L + y) W + w, W = ceil((L/2) / 64);    */
+/*   - x_{0,0} = lo32(seed) (seed 1 gives the paper's x_{0,0} = 1);     */
+/*   - each colour step advances every thread 64 times; the k-th new    */
+/*     value (k = 1..64) decides colour-local site 64 w + 64 - k of its */
+/*     row (site 63 of the word first); sites past L/2 use no value     */
+/*     but still advance the generator;                                 */
+/*   - accept an uphill move dE iff |int32(x)| < t'(dE) with            */
+/*     t'(dE) = min(floor(exp(-beta dE) 2^31), 2^31).                   */
+/* ================================================================== */
+
+uint32_t oracle_lcg_threshold(double beta, int dE)
+{
+    double w = exp(-beta * (double)dE);
+    double scaled = floor(ldexp(w, 31));
+    if (scaled >= 2147483648.0)
+        return 0x80000000u;
+    if (scaled <= 0.0)
+        return 0u;
+    return (uint32_t)scaled;
+}
+
+/* Thread seeds by the recurrence of Eq. (7): state[j] for j = 0 .. 2 L W - 1. */
+void oracle_lcg_seed(int64_t L, uint64_t seed, uint32_t *state)
+{
+    int64_t W = (L / 2 + 63) / 64;
+    uint32_t x = (uint32_t)seed;
+    for (int64_t j = 0; j < 2 * L * W; ++j) {
+        state[j] = x;
+        x = (uint32_t)((uint64_t)16807u * x);
+    }
+}
+
+static void lcg_colour_step(int64_t L, uint32_t t4, uint32_t t8, int colour, int8_t *s,
+                            uint32_t *state)
+{
+    int64_t half = L / 2, W = (L / 2 + 63) / 64;
+#pragma omp parallel for schedule(static)
+    for (int64_t y = 0; y < L; ++y) {
+        for (int64_t w = 0; w < W; ++w) {
+            uint32_t x = state[(colour * L + y) * W + w];
+            for (int k = 1; k <= 64; ++k) {
+                x = (uint32_t)((uint64_t)1664525u * x + 1013904223u);
+                int64_t site = 64 * w + 64 - k;       /* colour-local index in the row */
+                if (site >= half)
+                    continue;
+                int64_t px = 2 * site + ((y + colour) & 1);
+                int32_t sx = (int32_t)x;
+                uint32_t u = (uint32_t)(sx < 0 ? -(int64_t)sx : (int64_t)sx);
+                int v = s[y * L + px];
+                int n1 = s[y * L + wrap(px - 1, L)];
+                int n2 = s[y * L + wrap(px + 1, L)];
+                int n3 = s[wrap(y - 1, L) * L + px];
+                int n4 = s[wrap(y + 1, L) * L + px];
+                if (oracle_accept(v, n1, n2, n3, n4, u, t4, t8))
+                    s[y * L + px] = (int8_t)(-v);
+            }
+            state[(colour * L + y) * W + w] = x;
+        }
+    }
+}
+
+/* n sweeps with the per-thread LCG: colour 0 then colour 1, then       */
+/* (E, M) into EM (may be NULL).  t4, t8 from oracle_lcg_threshold.     */
+void oracle_lcg_sweeps(int64_t L, uint32_t t4, uint32_t t8, int64_t n, int8_t *s,
+                       uint32_t *state, int64_t *EM)
+{
+    for (int64_t k = 0; k < n; ++k) {
+        lcg_colour_step(L, t4, t8, 0, s, state);
+        lcg_colour_step(L, t4, t8, 1, s, state);
+        if (EM)
+            oracle_measure(L, s, &EM[2 * k], &EM[2 * k + 1]);
+    }
+}
+
 /* ------------------------------------------------------------------ */
 /* Light-cone window.  After n sweeps a site depends only on the       */
 /* initial spins and uniforms within Manhattan distance 2n (one site   */
