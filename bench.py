@@ -55,6 +55,8 @@ def parse():
                    help="plain workload: large = 16384^2 (the headline), huge = 262144^2 "
                         "(8 GiB, HBM-resident), small = 64^2, paper-4096 = 4096^2 at 0.99 T_c")
     p.add_argument("--no-served", action="store_true", help="skip the served request stream")
+    p.add_argument("--no-lcg", action="store_true",
+                   help="skip the plain workload with the paper's LCG random numbers")
     p.add_argument("--no-autotune", action="store_true",
                    help="use the default launch shape (profiling runs: no trial launches)")
     p.add_argument("--served-requests", type=int, default=200,
@@ -294,6 +296,41 @@ def bench_fss(torch, ising, dev, grid, EMs, discard, per_interval=8, nblocks=20)
             "tc_exact": round(2.0 / math.log(1.0 + math.sqrt(2.0)), 6)}
 
 
+# The paper's per-thread LCG dynamics: one v_mad_u64_u32 per uniform, then
+# for each threshold an add, a compare and a bit insert (|int32(x)| < t is
+# one unsigned range test): 7 lane-operations per spin update.
+LCG_OPS_PER_UPDATE = 7.0
+
+
+def bench_lcg(torch, ising, dev, w, steps):
+    """The plain workload with the paper's own random numbers (section 5.3)."""
+    lat = ising.Lattice(w.L, seed=w.seed, stream_id=w.stream_id, init=w.init, beta=1.0 / w.T,
+                        device=dev)
+    lat.use_lcg()
+    EM = torch.empty((w.sweeps, 2), dtype=torch.int64, device=dev)
+    stream = lat.stream
+    lat.sweep(w.sweeps, EM)
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(steps):
+        lat.sweep(w.sweeps, EM)
+    b.record(stream)
+    b.synchronize()
+    ms = a.elapsed_time(b)
+    N = w.L * w.L
+    launch_us = ms * 1e3 / (2 * w.sweeps * steps)
+    achieved = LCG_OPS_PER_UPDATE * (N / 2) / (launch_us * 1e-6)
+    last = EM[-1].cpu().tolist()
+    assert tuple(last) == lat.measure(), "fused E/M disagrees with a recount"
+    return {"value": round(N * w.sweeps * steps / (ms * 1e6), 2), "unit": "spin updates/ns",
+            "workload": "as the plain workload, per-thread LCG x <- 1664525 x + 1013904223 "
+                        "mod 2^32 per 64-site word (Eqs. (6), (7))",
+            "avg_launch_us": round(launch_us, 3), "ops_per_update": LCG_OPS_PER_UPDATE,
+            "roofline_frac": round(achieved / VALU_PEAK_LANE_OPS, 4)}
+
+
 def bench_fss_proof(torch, ising, dev, sweeps=200_000, discard=20_000, nblocks=20):
     """The paper's proof of concept (section 2): Binder cumulants of small
     lattices (L = 8..64, six temperatures in [2.15, 2.40], long runs on the
@@ -425,6 +462,10 @@ def main():
                         "max_blocks": tuned["max_blocks"],
                         "lds_resident_bytes": tuned["small_lds_bytes"]},
     }
+    if not args.no_lcg:
+        print("bench: plain workload with the paper's LCG random numbers", file=sys.stderr,
+              flush=True)
+        result["lcg"] = bench_lcg(torch, ising, dev, w, args.steps)
     if args.copy_calibration:
         # a plain copy of known size: 1 GiB read + 1 GiB written
         src = torch.ones(1 << 30, dtype=torch.uint8, device=dev)

@@ -227,6 +227,36 @@ ISING_API ising_status ising_tuning_lookup(int64_t L, ising_tuning *out);
 ISING_API ising_status ising_tuning_clear(void);
 
 /* ---------------------------------------------------------------- */
+/* The paper's own random numbers (alternative dynamics).            */
+/* ---------------------------------------------------------------- */
+
+#define ISING_RNG_PHILOX 0 /* counter-based Philox4x32-10 per site (the default) */
+#define ISING_RNG_LCG 1    /* per-thread linear congruential generators */
+
+/* Device bytes of the per-thread LCG states of a lattice of side L
+ * (2 * L * W uint32, W = ceil((L/2)/64)); 0 for an invalid L. */
+ISING_API size_t ising_lcg_bytes(int64_t L);
+
+/*
+ * Choose the random numbers of the Metropolis decisions (section 5.3).
+ * ISING_RNG_LCG uses one generator per 64-site word of each colour
+ * ("thread" j = (c L + y) W + w): x <- (1664525 x + 1013904223) mod 2^32
+ * (Eq. (6)), seeds x_{0,j} = lo32(seed) * 16807^j mod 2^32 (Eq. (7); seed 1
+ * gives the paper's x_{0,0} = 1).  Each colour step advances a word's
+ * generator 64 times; the k-th value decides site 64 - k of the word (site
+ * 63 first), and an uphill move dE is accepted iff |int32(x)| <
+ * min(floor(exp(-beta dE) 2^31), 2^31), i.e. y = |x / 2^31| < exp(-beta dE).
+ * The states live in dev_state (caller-owned device memory of
+ * ising_lcg_bytes(L) bytes, 4-byte aligned, kept for the handle's life); the
+ * call seeds them asynchronously on the handle's stream.  Needs L % 8 == 0
+ * (tiled layout); plain sweeps only (ising_multi_sweep rejects such
+ * handles); the hot start is unchanged.  ISING_RNG_PHILOX (dev_state
+ * ignored) returns to the default.  EINVAL / ENOMEM on bad arguments.
+ */
+ISING_API ising_status ising_set_rng(ising_t *h, int32_t kind, void *dev_state,
+                                     size_t state_bytes);
+
+/* ---------------------------------------------------------------- */
 /* Finite-size-scaling analysis of per-sweep (E, M) series.           */
 /* ---------------------------------------------------------------- */
 

@@ -3,6 +3,8 @@
 // and magnetisation reduction fused into the colour-1 pass, a measurement
 // pass, and a single-workgroup LDS-resident multi-sweep kernel for small
 // lattices.
+#include <algorithm>
+
 #include "ising_kernels.hpp"
 
 #include "ising_device.hpp"
@@ -402,7 +404,7 @@ __device__ __forceinline__ void process_tile(const TileArgs& a, const TileLane& 
 // shared by neighbouring lanes hit in L1/L2), issues the loads before the
 // Philox stretch and uses them after it.  No block barrier: the four waves
 // of a workgroup work independently.
-template <bool FULL, int WIDEM, bool BUMP_SALU = false>
+template <bool FULL, int WIDEM, bool BUMP_SALU = false, bool LCG = false>
 __device__ __forceinline__ void process_tile_direct(const TileArgs& a, const TileLane& tl,
                                                     int colour, bool em, int64_t tidx,
                                                     uint32_t& anti, uint32_t& up) {
@@ -431,19 +433,27 @@ __device__ __forceinline__ void process_tile_direct(const TileArgs& a, const Til
     const uint64_t n2 = other[ym * W + w];
     const uint64_t n3 = other[yp * W + w];
     const uint64_t sd = other[y * W + ws];
-    uint32_t lo, hi;
-    if (a.hi_mode == 0) {
-      lo = (uint32_t)y * (uint32_t)g.L8 + 16u * (uint32_t)w;
-      hi = 0;
-    } else {
-      const uint64_t gy =
-          (uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)y) * (uint64_t)g.L8;
-      hi = (uint32_t)(gy >> 32);
-      lo = (uint32_t)gy + 16u * (uint32_t)w;
-    }
-    const int nq = (FULL || w < W - 1) ? 16 : (g.nb_last >> 2);
     uint64_t r4, r8;
-    masks_shift<FULL, BUMP_SALU>(lo, hi, nq, a.k0, a.k1, a.t, ctr3, a.t4, a.t8, r4, r8);
+    if (LCG) {
+      // this word's generator: thread (colour L + y) W + w
+      uint32_t* xs = a.lcg + ((int64_t)colour * g.L + y) * W + w;
+      uint32_t x = *xs;
+      masks_lcg(x, a.l4d, a.l4m, a.l8d, a.l8m, r4, r8);
+      *xs = x;
+    } else {
+      uint32_t lo, hi;
+      if (a.hi_mode == 0) {
+        lo = (uint32_t)y * (uint32_t)g.L8 + 16u * (uint32_t)w;
+        hi = 0;
+      } else {
+        const uint64_t gy =
+            (uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)y) * (uint64_t)g.L8;
+        hi = (uint32_t)(gy >> 32);
+        lo = (uint32_t)gy + 16u * (uint32_t)w;
+      }
+      const int nq = (FULL || w < W - 1) ? 16 : (g.nb_last >> 2);
+      masks_shift<FULL, BUMP_SALU>(lo, hi, nq, a.k0, a.k1, a.t, ctr3, a.t4, a.t8, r4, r8);
+    }
     __builtin_amdgcn_sched_barrier(0);
     Nbr n;
     n.n0 = n0;
@@ -465,7 +475,7 @@ __device__ __forceinline__ void process_tile_direct(const TileArgs& a, const Til
 
 // Tiles read their neighbour words directly (process_tile_direct): no LDS
 // staging and no barrier until the E/M reduction at the end.
-template <int C, bool EM, bool FULL, bool WIDE>
+template <int C, bool EM, bool FULL, bool WIDE, bool LCG>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_tile_sweep(
     TileArgs a) {
   __shared__ uint64_t red64[8];
@@ -479,7 +489,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
   uint32_t anti = 0, up = 0;
   const TileLane tl = tile_lane<WIDE ? 1 : 0>(a);
   for (int64_t tidx = lb; tidx < a.tiles; tidx += G)
-    process_tile_direct<FULL, WIDE ? 1 : 0>(a, tl, C, EM, tidx, anti, up);
+    process_tile_direct<FULL, WIDE ? 1 : 0, false, LCG>(a, tl, C, EM, tidx, anti, up);
   if (C == 1 && EM) {
     block_sum2(anti, up, red);
     if (threadIdx.x == 0) {
@@ -780,12 +790,13 @@ hipError_t launch_advance(hipStream_t st, uint32_t* kbase, uint32_t by) {
 // ---------------------------------------------------------------------
 // Host-side launchers
 // ---------------------------------------------------------------------
-hipError_t launch_tile_sweep(hipStream_t st, int colour, const TileArgs& a, int blocks) {
+template <bool LCG>
+static void launch_tile_sweep_rng(hipStream_t st, int colour, const TileArgs& a, int blocks) {
   const bool em = (colour == 1) ? (a.part != nullptr) : false;
   const bool full = a.g.nb_last == 64;
   const bool wide = a.g.W >= kWideMinWords;
 #define ISING_TILE(C, E, F, WI) \
-  hipLaunchKernelGGL((k_tile_sweep<C, E, F, WI>), dim3(blocks), dim3(256), 0, st, a)
+  hipLaunchKernelGGL((k_tile_sweep<C, E, F, WI, LCG>), dim3(blocks), dim3(256), 0, st, a)
 #define ISING_TILE_FW(C, E)                                   \
   do {                                                        \
     if (full) {                                               \
@@ -804,6 +815,33 @@ hipError_t launch_tile_sweep(hipStream_t st, int colour, const TileArgs& a, int 
     ISING_TILE_FW(1, false);
 #undef ISING_TILE_FW
 #undef ISING_TILE
+}
+
+hipError_t launch_tile_sweep(hipStream_t st, int colour, const TileArgs& a, int blocks) {
+  if (a.lcg)
+    launch_tile_sweep_rng<true>(st, colour, a, blocks);
+  else
+    launch_tile_sweep_rng<false>(st, colour, a, blocks);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_lcg_seed(uint32_t* state, int64_t n, uint32_t s0) {
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n;
+       j += (int64_t)gridDim.x * blockDim.x) {
+    // 16807^j mod 2^32 by square and multiply
+    uint32_t p = 1u, b = 16807u;
+    for (uint64_t e = (uint64_t)j; e; e >>= 1) {
+      if (e & 1u) p *= b;
+      b *= b;
+    }
+    state[j] = s0 * p;
+  }
+}
+
+hipError_t launch_lcg_seed(hipStream_t st, uint32_t* state, int64_t n, uint32_t s0) {
+  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_lcg_seed, dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(256), 0, st,
+                     state, n, s0);
   return hipGetLastError();
 }
 

@@ -54,6 +54,10 @@ struct TileArgs {
   int64_t* prev_EM;           // colour 0: (E, M) slot of the previous sweep to finalise
   const uint64_t* prev_part;  // partials of the previous sweep
   int32_t prev_blocks;
+  // per-thread LCG dynamics (plain tiles only): states [2][L][W], or null
+  // for Philox; decision (x + d) < m per threshold (see ising_device.hpp)
+  uint32_t* lcg;
+  uint32_t l4d, l4m, l8d, l8m;
 };
 
 hipError_t launch_tile_sweep(hipStream_t st, int colour, const TileArgs& a, int blocks);
@@ -62,6 +66,8 @@ hipError_t launch_tile_sweep(hipStream_t st, int colour, const TileArgs& a, int 
 hipError_t launch_strip_sweep(hipStream_t st, int colour, const TileArgs& a, int blocks);
 hipError_t launch_finalize_em(hipStream_t st, const uint64_t* part, int blocks, int64_t L,
                               int64_t* EM);
+// Thread seeds of the LCG dynamics: state[j] = s0 * 16807^j mod 2^32.
+hipError_t launch_lcg_seed(hipStream_t st, uint32_t* state, int64_t n, uint32_t s0);
 
 // Batched sweeps (see ising_kernels.hip).
 struct FusedLattice {

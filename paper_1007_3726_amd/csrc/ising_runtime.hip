@@ -66,6 +66,16 @@ uint32_t metropolis_threshold(double beta, int dE) {
   return (uint32_t)scaled;
 }
 
+// Threshold of the per-thread LCG dynamics (uniform |int32(x)| / 2^31):
+// floor(exp(-beta dE) 2^31), clamped to 2^31.
+uint32_t lcg_threshold(double beta, int dE) {
+  const double factor = std::exp(-beta * (double)dE);
+  const double scaled = std::floor(std::ldexp(factor, 31));
+  if (scaled >= 2147483648.0) return 0x80000000u;
+  if (scaled <= 0.0) return 0u;
+  return (uint32_t)scaled;
+}
+
 int grid_blocks(int64_t work_items, int threads, int max_blocks) {
   int64_t b = (work_items + threads - 1) / threads;
   if (b > max_blocks) b = max_blocks;
@@ -89,7 +99,7 @@ SweepArgs sweep_args(const ising_lattice* h, uint32_t t, int64_t* EM) {
 }
 
 bool strip_form(const ising_lattice* h) {
-  return h->tune.form == 1 && h->g.W >= kWideMinWords;
+  return h->tune.form == 1 && h->g.W >= kWideMinWords && h->lcg == nullptr;
 }
 
 // Shape of the tiled half-sweep for this lattice; false when it does not
@@ -162,7 +172,14 @@ bool strip_args(const ising_lattice* h, TileArgs* out) {
 }
 
 bool use_small_path(const ising_lattice* h) {
-  return 2 * h->plane_words * (int64_t)sizeof(uint64_t) <= h->tune.small_lds_bytes;
+  return h->lcg == nullptr &&
+         2 * h->plane_words * (int64_t)sizeof(uint64_t) <= h->tune.small_lds_bytes;
+}
+
+// (d, m) of the LCG decision (x + d) < m for threshold t' (ising_device.hpp)
+static void lcg_decision(uint32_t t, uint32_t* d, uint32_t* m) {
+  *d = t ? t - 1u : 0u;
+  *m = t ? (uint32_t)(2ull * t - 1ull) : 0u;
 }
 
 ising_status enqueue_sweeps(ising_lattice* h, int64_t n, int64_t* dev_EM) {
@@ -192,6 +209,9 @@ ising_status enqueue_sweeps(ising_lattice* h, int64_t n, int64_t* dev_EM) {
     const int blocks = (int)std::min<int64_t>(units, std::min(h->tune.max_blocks,
                                                               kMaxSweepBlocks));
     auto launch = strip ? launch_strip_sweep : launch_tile_sweep;
+    ta.lcg = h->lcg;
+    lcg_decision(h->l4, &ta.l4d, &ta.l4m);
+    lcg_decision(h->l8, &ta.l8d, &ta.l8m);
     for (int64_t k = 0; k < n; ++k) {
       ta.t = (uint32_t)(h->sweep + (uint64_t)k);
       ta.prev_EM = (dev_EM && k > 0) ? dev_EM + 2 * (k - 1) : nullptr;
@@ -212,6 +232,7 @@ ising_status enqueue_sweeps(ising_lattice* h, int64_t n, int64_t* dev_EM) {
     }
     return ISING_OK;
   }
+  if (h->lcg) return fail(ISING_EINVAL, "LCG dynamics need the tiled layout (L %% 8 == 0)");
   const int blocks = grid_blocks(h->plane_words, 256, h->tune.max_blocks);
   for (int64_t k = 0; k < n; ++k) {
     const uint32_t t = (uint32_t)(h->sweep + (uint64_t)k);
@@ -313,7 +334,37 @@ ising_status ising_set_beta(ising_t* h, double beta) {
   h->beta = beta;
   h->t4 = metropolis_threshold(beta, 4);
   h->t8 = metropolis_threshold(beta, 8);
+  h->l4 = lcg_threshold(beta, 4);
+  h->l8 = lcg_threshold(beta, 8);
   h->beta_set = true;
+  return ISING_OK;
+}
+
+size_t ising_lcg_bytes(int64_t L) {
+  if (L < 4 || (L & 1) || L > kMaxL) return 0;
+  return (size_t)2 * (size_t)L * (size_t)words_per_row(L) * sizeof(uint32_t);
+}
+
+ising_status ising_set_rng(ising_t* h, int32_t kind, void* dev_state, size_t state_bytes) {
+  clear_error();
+  if (!h) return fail(ISING_EINVAL, "ising_set_rng: NULL handle");
+  if (kind == ISING_RNG_PHILOX) {
+    h->lcg = nullptr;
+    return ISING_OK;
+  }
+  if (kind != ISING_RNG_LCG) return fail(ISING_EINVAL, "ising_set_rng: unknown kind %d", kind);
+  TileArgs ta;
+  if (!tile_args(h, &ta))
+    return fail(ISING_EINVAL, "ising_set_rng: LCG dynamics need L %% 8 == 0 (tiled layout)");
+  const size_t need = ising_lcg_bytes(h->L);
+  if (!dev_state || state_bytes < need)
+    return fail(ISING_ENOMEM, "ising_set_rng: state buffer of %zu bytes needed", need);
+  if (((uintptr_t)dev_state & 3u) != 0)
+    return fail(ISING_EINVAL, "ising_set_rng: state buffer must be 4-byte aligned");
+  hipError_t e = launch_lcg_seed(h->stream, (uint32_t*)dev_state, (int64_t)(need / 4),
+                                 (uint32_t)h->seed);
+  if (e != hipSuccess) return hip_fail(e, "ising_set_rng: seeding");
+  h->lcg = (uint32_t*)dev_state;
   return ISING_OK;
 }
 

@@ -35,6 +35,7 @@ int64_t words_per_row(int64_t L);
 size_t lattice_bytes(int64_t L);
 Geom make_geom(int64_t L);
 uint32_t metropolis_threshold(double beta, int dE);
+uint32_t lcg_threshold(double beta, int dE);
 int grid_blocks(int64_t work_items, int threads, int max_blocks);
 
 }  // namespace ising
@@ -52,7 +53,9 @@ struct ising_lattice {
   int32_t init;
   double beta;
   uint32_t t4, t8;
+  uint32_t l4, l8;      // LCG thresholds min(floor(exp(-beta dE) 2^31), 2^31)
   bool beta_set;
+  uint32_t* lcg;        // device: per-thread LCG states [2][L][W] (caller's), or null
   uint64_t sweep;       // counter of the next sweep
   hipStream_t stream;
   int device;

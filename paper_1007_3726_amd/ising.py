@@ -22,6 +22,8 @@ ISING_ENOTFOUND = -4
 ISING_ERANGE = -5
 ISING_FORM_TILE = 0
 ISING_FORM_STRIP = 1
+ISING_RNG_PHILOX = 0
+ISING_RNG_LCG = 1
 
 INIT_COLD_UP = 0
 INIT_COLD_DOWN = 1
@@ -107,6 +109,8 @@ def lib():
         "ising_server_inject_fault": ([vp, i64], i32),
         "ising_server_stats": ([vp, P(i64)], i32),
         "ising_server_destroy": ([vp], i32),
+        "ising_lcg_bytes": ([i64], ctypes.c_size_t),
+        "ising_set_rng": ([vp, i32, vp, ctypes.c_size_t], i32),
         "ising_reweight": ([i32, P(vp), P(i64), P(i64), P(ctypes.c_double), i32, P(i32),
                             P(ctypes.c_double), i32, vp, vp, vp], i32),
         "ising_fss_moments": ([vp, i32, i32, P(i64), vp, vp, vp], i32),
@@ -133,6 +137,12 @@ def _stream_ptr(stream) -> int:
     return int(stream.cuda_stream)
 
 
+def torch_uint32():
+    """A 4-byte torch dtype for viewing uint32 buffers (bit pattern only)."""
+    import torch
+    return torch.int32
+
+
 def _dev_alloc(nbytes: int, device):
     import torch
     return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
@@ -143,6 +153,10 @@ def _dev_alloc(nbytes: int, device):
 # ---------------------------------------------------------------------------
 def ising_lattice_bytes(L: int) -> int:
     return int(lib().ising_lattice_bytes(L))
+
+
+def ising_lcg_bytes(L: int) -> int:
+    return int(lib().ising_lcg_bytes(L))
 
 
 def ising_version() -> str:
@@ -182,6 +196,24 @@ class Lattice:
 
     def set_beta(self, beta: float):
         check(lib().ising_set_beta(self.h, float(beta)))
+
+    def use_lcg(self):
+        """Switch to the paper's per-thread LCG dynamics (ising_set_rng); the
+        state buffer is allocated here and seeded on the lattice's stream."""
+        nbytes = ising_lcg_bytes(self.L)
+        self.lcg_buf = _dev_alloc(max(nbytes, 4), self.device)
+        check(lib().ising_set_rng(self.h, ISING_RNG_LCG, self.lcg_buf.data_ptr(), nbytes))
+
+    def use_philox(self):
+        check(lib().ising_set_rng(self.h, ISING_RNG_PHILOX, None, 0))
+        self.lcg_buf = None
+
+    def lcg_states(self):
+        """Host copy of the LCG states as uint32 (2, L, W)."""
+        import numpy as np
+        W = (self.L // 2 + 63) // 64
+        self.stream.synchronize()
+        return self.lcg_buf.view(torch_uint32()).cpu().numpy().view(np.uint32).reshape(2, self.L, W)
 
     def thresholds(self):
         t = (ctypes.c_uint32 * 2)()

@@ -1,0 +1,116 @@
+"""The per-thread-LCG dynamics (the paper's own random numbers) on the GPU
+against the oracle's LCG mode: bit-exact spins, per-sweep int64 (E, M) and
+generator states, on ragged lattices (partial last words, one-word rows,
+W = 65), at several temperatures including beta = 0 and +inf; seeding;
+checkpoint/resume of spins and states; argument checks."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def I():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1007_3726_amd import ising
+    ising.lib()
+    return ising
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _lcg_lattice(I, L, seed, init, beta):
+    lat = I.Lattice(L, seed=seed, stream_id=0, init=init, beta=beta)
+    lat.use_lcg()
+    return lat
+
+
+@pytest.mark.parametrize("L", [8, 16, 24, 64, 136, 200])
+@pytest.mark.parametrize("beta", [1 / 2.269185, 0.0, math.inf, 1 / 1.5])
+def test_every_sweep_bit_exact(I, L, beta):
+    n = 10
+    _say("case L=%d beta=%r" % (L, beta))
+    lat = _lcg_lattice(I, L, 7, workloads.INIT_HOT, beta)
+    assert np.array_equal(lat.lcg_states(), oracle.lcg_seed(L, 7))
+    s = oracle.init(L, 7, 0, workloads.INIT_HOT)
+    st = oracle.lcg_seed(L, 7)
+    for t in range(n):
+        em = lat.sweep_em(1).cpu().numpy()
+        oem = oracle.lcg_sweeps(s, beta, st, 1)
+        assert np.array_equal(em, oem), t
+        assert np.array_equal(lat.get_spins(), s), t
+    assert np.array_equal(lat.lcg_states(), st)
+
+
+@pytest.mark.parametrize("L,seed,init", [(1024, 3, workloads.INIT_HOT),
+                                         (2056, 12345, workloads.INIT_COLD_UP),
+                                         (8320, 1, workloads.INIT_HOT)])
+def test_larger_lattices(I, L, seed, init):
+    n = 3
+    beta = 1 / 2.3
+    _say("case L=%d" % L)
+    lat = _lcg_lattice(I, L, seed, init, beta)
+    em = lat.sweep_em(n).cpu().numpy()
+    s = oracle.init(L, seed, 0, init)
+    st = oracle.lcg_seed(L, seed)
+    oem = oracle.lcg_sweeps(s, beta, st, n)
+    assert np.array_equal(em, oem)
+    assert np.array_equal(lat.get_spins(), s)
+    assert np.array_equal(lat.lcg_states(), st)
+
+
+def test_checkpoint_and_resume(I):
+    import torch
+    L, beta = 136, 0.42
+    a = _lcg_lattice(I, L, 4, workloads.INIT_HOT, beta)
+    a.sweep(12)
+    full = a.get_spins()
+    b = _lcg_lattice(I, L, 4, workloads.INIT_HOT, beta)
+    b.sweep(5)
+    spins, states = b.get_spins(), b.lcg_states().copy()
+    c = _lcg_lattice(I, L, 99, workloads.INIT_COLD_DOWN, beta)
+    c.set_spins(spins)
+    c.lcg_buf.copy_(torch.from_numpy(states.view(np.int32).reshape(-1)).view(torch.uint8).cuda())
+    c.sweep(7)
+    assert np.array_equal(c.get_spins(), full)
+
+
+def test_philox_and_lcg_switch(I):
+    L, beta = 64, 0.4
+    a = I.Lattice(L, seed=2, init=workloads.INIT_HOT, beta=beta)
+    ref = a.sweep_em(4).cpu().numpy()
+    b = I.Lattice(L, seed=2, init=workloads.INIT_HOT, beta=beta)
+    b.use_lcg()
+    b.use_philox()
+    assert np.array_equal(b.sweep_em(4).cpu().numpy(), ref)
+
+
+def test_argument_checks(I):
+    import torch
+    lat = I.Lattice(66, init=workloads.INIT_HOT, beta=0.4)  # L % 8 != 0
+    buf = torch.empty(I.ising_lcg_bytes(66), dtype=torch.uint8, device="cuda")
+    with pytest.raises(I.IsingError):
+        I.check(I.lib().ising_set_rng(lat.h, I.ISING_RNG_LCG, buf.data_ptr(), buf.numel()))
+    lat2 = I.Lattice(64, init=workloads.INIT_HOT, beta=0.4)
+    small = torch.empty(16, dtype=torch.uint8, device="cuda")
+    with pytest.raises(I.IsingError) as e:
+        I.check(I.lib().ising_set_rng(lat2.h, I.ISING_RNG_LCG, small.data_ptr(), 16))
+    assert e.value.code == I.ISING_ENOMEM
+    with pytest.raises(I.IsingError):
+        I.check(I.lib().ising_set_rng(lat2.h, 7, None, 0))
+    lat2.use_lcg()
+    EM = torch.empty((2, 2), dtype=torch.int64, device="cuda")
+    with pytest.raises(I.IsingError):
+        I.multi_sweep([lat2], 2, [EM])  # batched path is Philox only
+    assert I.ising_lcg_bytes(64) == 2 * 64 * 1 * 4 and I.ising_lcg_bytes(7) == 0
