@@ -296,10 +296,11 @@ def bench_fss(torch, ising, dev, grid, EMs, discard, per_interval=8, nblocks=20)
             "tc_exact": round(2.0 / math.log(1.0 + math.sqrt(2.0)), 6)}
 
 
-# The paper's per-thread LCG dynamics: one v_mad_u64_u32 per uniform, then
-# for each threshold an add, a compare and a bit insert (|int32(x)| < t is
-# one unsigned range test): 7 lane-operations per spin update.
-LCG_OPS_PER_UPDATE = 7.0
+# The paper's per-thread LCG dynamics: one v_mad_u64_u32 per uniform (the
+# chain runs on a shifted state so that the first range test is a bare
+# compare), one add for the second range test, two compares and two bit
+# inserts: 6 lane-operations per spin update.
+LCG_OPS_PER_UPDATE = 6.0
 
 
 def bench_lcg(torch, ising, dev, w, steps):

@@ -237,13 +237,16 @@ __device__ __forceinline__ void masks_shift(uint32_t lo, uint32_t hi, int nq, ui
 // one colour.  The uniform of a value is |int32(x)| / 2^31, and an uphill
 // move with threshold t' = floor(exp(-beta dE) 2^31) is accepted iff
 // |int32(x)| < t'.  For integers that is x + (t' - 1) < 2 t' - 1 (mod 2^32)
-// when t' >= 1, and never when t' = 0; the host passes (d, m) = (t' - 1,
-// 2 t' - 1), or (0, 0) for t' = 0, so the test is (x + d) < m.
+// when t' >= 1, and never when t' = 0; with (d, m) = (t' - 1, 2 t' - 1), or
+// (0, 0) for t' = 0, the test is (x + d) < m.
 // ---------------------------------------------------------------------
 constexpr uint32_t kLcgA = 1664525u;
 constexpr uint32_t kLcgC = 1013904223u;
 
-__device__ __forceinline__ uint32_t lcg_next(uint32_t x) {
+// The chain runs on z = x + d4 instead of x: z' = a z + (c + d4 - a d4), still
+// one multiply-add, and the t4 test becomes the bare compare z < m4; the t8
+// test is (z + e) < m8 with e = d8 - d4.  6 lane-operations per site.
+__device__ __forceinline__ uint32_t lcg_next(uint32_t z, uint32_t c) {
   // one full-rate v_mad_u64_u32 per value (the low word is the next state;
   // the multiplier sits in a VGPR: one SGPR operand per VOP3 on gfx9);
   // written out so that the compiler keeps the chain instead of rewriting
@@ -251,39 +254,34 @@ __device__ __forceinline__ uint32_t lcg_next(uint32_t x) {
   uint64_t r, carry;
   asm("v_mad_u64_u32 %0, %1, %2, %3, %4"
       : "=v"(r), "=s"(carry)
-      : "v"(x), "v"(kLcgA), "s"((uint64_t)kLcgC));
+      : "v"(z), "v"(kLcgA), "s"((uint64_t)c));
   return (uint32_t)r;
 }
 
-// Shift the decisions of four consecutive LCG values (g1 first) into the
-// accumulators: acc = 2 acc + [g + d < m], g1's bit ending highest.  Every
-// compare writes its own SGPR pair, read as carry-in at least three
-// instructions later (gfx950 needs two wait states).
+// Shift the decisions of four consecutive values (g1 first) into the
+// accumulators: a4 = 2 a4 + [g < m4], a8 = 2 a8 + [g + e < m8], g1's bit
+// ending highest.  Every compare writes its own SGPR pair, read as carry-in
+// at least three instructions later (gfx950 needs two wait states).
 __device__ __forceinline__ void shift_in4_lcg(uint32_t& a4, uint32_t& a8, uint32_t g1,
-                                              uint32_t g2, uint32_t g3, uint32_t g4,
-                                              uint32_t d4, uint32_t m4, uint32_t d8,
-                                              uint32_t m8) {
+                                              uint32_t g2, uint32_t g3, uint32_t g4, uint32_t e,
+                                              uint32_t m4, uint32_t m8) {
   uint64_t c0, c1, c2, c3, dd;
   uint32_t u0, u1, u2, u3;
-  asm("v_add_u32_e32 %[u0], %[d4], %[g1]\n\t"
-      "v_add_u32_e32 %[u1], %[d8], %[g1]\n\t"
-      "v_add_u32_e32 %[u2], %[d4], %[g2]\n\t"
-      "v_add_u32_e32 %[u3], %[d8], %[g2]\n\t"
-      "v_cmp_gt_u32_e64 %[c0], %[m4], %[u0]\n\t"
-      "v_cmp_gt_u32_e64 %[c1], %[m8], %[u1]\n\t"
-      "v_cmp_gt_u32_e64 %[c2], %[m4], %[u2]\n\t"
-      "v_cmp_gt_u32_e64 %[c3], %[m8], %[u3]\n\t"
+  asm("v_add_u32_e32 %[u0], %[e], %[g1]\n\t"
+      "v_add_u32_e32 %[u1], %[e], %[g2]\n\t"
+      "v_cmp_gt_u32_e64 %[c0], %[m4], %[g1]\n\t"
+      "v_cmp_gt_u32_e64 %[c1], %[m8], %[u0]\n\t"
+      "v_cmp_gt_u32_e64 %[c2], %[m4], %[g2]\n\t"
+      "v_cmp_gt_u32_e64 %[c3], %[m8], %[u1]\n\t"
+      "v_add_u32_e32 %[u2], %[e], %[g3]\n\t"
       "v_addc_co_u32_e64 %[a4], %[dd], %[a4], %[a4], %[c0]\n\t"
       "v_addc_co_u32_e64 %[a8], %[dd], %[a8], %[a8], %[c1]\n\t"
-      "v_add_u32_e32 %[u0], %[d4], %[g3]\n\t"
-      "v_add_u32_e32 %[u1], %[d8], %[g3]\n\t"
+      "v_add_u32_e32 %[u3], %[e], %[g4]\n\t"
       "v_addc_co_u32_e64 %[a4], %[dd], %[a4], %[a4], %[c2]\n\t"
       "v_addc_co_u32_e64 %[a8], %[dd], %[a8], %[a8], %[c3]\n\t"
-      "v_cmp_gt_u32_e64 %[c0], %[m4], %[u0]\n\t"
-      "v_cmp_gt_u32_e64 %[c1], %[m8], %[u1]\n\t"
-      "v_add_u32_e32 %[u2], %[d4], %[g4]\n\t"
-      "v_add_u32_e32 %[u3], %[d8], %[g4]\n\t"
-      "v_cmp_gt_u32_e64 %[c2], %[m4], %[u2]\n\t"
+      "v_cmp_gt_u32_e64 %[c0], %[m4], %[g3]\n\t"
+      "v_cmp_gt_u32_e64 %[c1], %[m8], %[u2]\n\t"
+      "v_cmp_gt_u32_e64 %[c2], %[m4], %[g4]\n\t"
       "v_cmp_gt_u32_e64 %[c3], %[m8], %[u3]\n\t"
       "v_addc_co_u32_e64 %[a4], %[dd], %[a4], %[a4], %[c0]\n\t"
       "v_addc_co_u32_e64 %[a8], %[dd], %[a8], %[a8], %[c1]\n\t"
@@ -292,26 +290,27 @@ __device__ __forceinline__ void shift_in4_lcg(uint32_t& a4, uint32_t& a8, uint32
       : [a4] "+v"(a4), [a8] "+v"(a8), [c0] "=&s"(c0), [c1] "=&s"(c1), [c2] "=&s"(c2),
         [c3] "=&s"(c3), [dd] "=&s"(dd), [u0] "=&v"(u0), [u1] "=&v"(u1), [u2] "=&v"(u2),
         [u3] "=&v"(u3)
-      : [g1] "v"(g1), [g2] "v"(g2), [g3] "v"(g3), [g4] "v"(g4), [d4] "s"(d4), [m4] "s"(m4),
-        [d8] "s"(d8), [m8] "s"(m8));
+      : [g1] "v"(g1), [g2] "v"(g2), [g3] "v"(g3), [g4] "v"(g4), [e] "s"(e), [m4] "s"(m4),
+        [m8] "s"(m8));
 }
 
-// r4 / r8 of one word from its LCG state x (advanced 64 times): the k-th
-// new value decides site 64 - k of the word (site 63 first).
-__device__ __forceinline__ void masks_lcg(uint32_t& x, uint32_t d4, uint32_t m4, uint32_t d8,
+// r4 / r8 of one word from its shifted LCG state z = x + d4 (advanced 64
+// times): the k-th new value decides site 64 - k of the word (site 63
+// first).  c = 1013904223 + d4 - 1664525 d4 (mod 2^32), e = d8 - d4.
+__device__ __forceinline__ void masks_lcg(uint32_t& z, uint32_t c, uint32_t e, uint32_t m4,
                                           uint32_t m8, uint64_t& r4, uint64_t& r8) {
   uint32_t a4_hi = 0, a8_hi = 0, a4_lo = 0, a8_lo = 0;
 #pragma unroll
   for (int q = 0; q < 16; ++q) {
-    const uint32_t g1 = lcg_next(x);
-    const uint32_t g2 = lcg_next(g1);
-    const uint32_t g3 = lcg_next(g2);
-    const uint32_t g4 = lcg_next(g3);
-    x = g4;
+    const uint32_t g1 = lcg_next(z, c);
+    const uint32_t g2 = lcg_next(g1, c);
+    const uint32_t g3 = lcg_next(g2, c);
+    const uint32_t g4 = lcg_next(g3, c);
+    z = g4;
     if (q < 8)
-      shift_in4_lcg(a4_hi, a8_hi, g1, g2, g3, g4, d4, m4, d8, m8);
+      shift_in4_lcg(a4_hi, a8_hi, g1, g2, g3, g4, e, m4, m8);
     else
-      shift_in4_lcg(a4_lo, a8_lo, g1, g2, g3, g4, d4, m4, d8, m8);
+      shift_in4_lcg(a4_lo, a8_lo, g1, g2, g3, g4, e, m4, m8);
   }
   r4 = ((uint64_t)a4_hi << 32) | a4_lo;
   r8 = ((uint64_t)a8_hi << 32) | a8_lo;

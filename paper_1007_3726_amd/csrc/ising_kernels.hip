@@ -437,9 +437,9 @@ __device__ __forceinline__ void process_tile_direct(const TileArgs& a, const Til
     if (LCG) {
       // this word's generator: thread (colour L + y) W + w
       uint32_t* xs = a.lcg + ((int64_t)colour * g.L + y) * W + w;
-      uint32_t x = *xs;
-      masks_lcg(x, a.l4d, a.l4m, a.l8d, a.l8m, r4, r8);
-      *xs = x;
+      uint32_t z = *xs + a.l4d;
+      masks_lcg(z, a.lc, a.le, a.l4m, a.l8m, r4, r8);
+      *xs = z - a.l4d;
     } else {
       uint32_t lo, hi;
       if (a.hi_mode == 0) {

@@ -55,9 +55,10 @@ struct TileArgs {
   const uint64_t* prev_part;  // partials of the previous sweep
   int32_t prev_blocks;
   // per-thread LCG dynamics (plain tiles only): states [2][L][W], or null
-  // for Philox; decision (x + d) < m per threshold (see ising_device.hpp)
+  // for Philox; the chain runs on z = x + l4d with addend lc, the tests are
+  // z < l4m and z + le < l8m (see ising_device.hpp)
   uint32_t* lcg;
-  uint32_t l4d, l4m, l8d, l8m;
+  uint32_t l4d, lc, le, l4m, l8m;
 };
 
 hipError_t launch_tile_sweep(hipStream_t st, int colour, const TileArgs& a, int blocks);

@@ -210,8 +210,11 @@ ising_status enqueue_sweeps(ising_lattice* h, int64_t n, int64_t* dev_EM) {
                                                               kMaxSweepBlocks));
     auto launch = strip ? launch_strip_sweep : launch_tile_sweep;
     ta.lcg = h->lcg;
+    uint32_t l8d = 0;
     lcg_decision(h->l4, &ta.l4d, &ta.l4m);
-    lcg_decision(h->l8, &ta.l8d, &ta.l8m);
+    lcg_decision(h->l8, &l8d, &ta.l8m);
+    ta.lc = kLcgC + ta.l4d - kLcgA * ta.l4d;  // addend of the chain on z = x + l4d
+    ta.le = l8d - ta.l4d;
     for (int64_t k = 0; k < n; ++k) {
       ta.t = (uint32_t)(h->sweep + (uint64_t)k);
       ta.prev_EM = (dev_EM && k > 0) ? dev_EM + 2 * (k - 1) : nullptr;
