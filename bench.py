@@ -58,7 +58,7 @@ def parse():
     p.add_argument("--no-lcg", action="store_true",
                    help="skip the plain workload with the paper's LCG random numbers")
     p.add_argument("--no-autotune", action="store_true",
-                   help="use the default launch shape (profiling runs: no trial launches)")
+                   help="skip the autotuner report (profiling runs: no trial launches)")
     p.add_argument("--served-requests", type=int, default=200,
                    help="requests of the 2000-request Poisson stream to serve (default: the "
                         "first 200, about 20 s)")
@@ -398,11 +398,21 @@ def main():
     stream = torch.cuda.current_stream(dev)
     # the autotuner picks the launch shape for this lattice size (well under a
     # second; a few seconds for 262144^2)
-    if args.no_autotune:
-        tuned = ising.tuning_lookup(w.L)
-    else:
-        tuned = ising.autotune(w.L, trial_sweeps=max(2, min(50, int(4e9 / (w.L * w.L)))),
-                               device=dev, stream=stream)
+    # the headline runs the default launch shape (the one the committed
+    # rocprofv3 summaries cover); the autotuner's pick for this side is
+    # timed and reported beside it, then removed again
+    autotuned = None
+    if not args.no_autotune:
+        t_at = time.perf_counter()
+        pick = ising.autotune(w.L, trial_sweeps=max(2, min(100, int(2.7e10 / (w.L * w.L)))),
+                              device=dev, stream=stream)
+        autotuned = {"form": ["tile", "strip"][pick["form"]], "rpw": pick["rpw"],
+                     "max_blocks": pick["max_blocks"],
+                     "lds_resident_bytes": pick["small_lds_bytes"],
+                     "updates_per_ns": round(pick["updates_per_ns"], 1),
+                     "seconds": round(time.perf_counter() - t_at, 3)}
+        ising.tuning_clear()
+    tuned = ising.tuning_lookup(w.L)
     kernel = plain_kernel(ising, w.L, tuned)
     lat = ising.Lattice(w.L, seed=w.seed, stream_id=w.stream_id, init=w.init, beta=1.0 / w.T,
                         device=dev, stream=stream)
@@ -459,9 +469,10 @@ def main():
                      "kernel": kernel, "avg_launch_us": round(launch_us, 3),
                      "ops_per_update": ALU_OPS_PER_UPDATE},
         "wall_s": round(wall, 3),
-        "tuned_shape": {"form": ["tile", "strip"][tuned["form"]], "rpw": tuned["rpw"],
-                        "max_blocks": tuned["max_blocks"],
-                        "lds_resident_bytes": tuned["small_lds_bytes"]},
+        "shape": {"form": ["tile", "strip"][tuned["form"]], "rpw": tuned["rpw"],
+                  "max_blocks": tuned["max_blocks"],
+                  "lds_resident_bytes": tuned["small_lds_bytes"]},
+        "autotuner_pick": autotuned,
     }
     if not args.no_lcg:
         print("bench: plain workload with the paper's LCG random numbers", file=sys.stderr,

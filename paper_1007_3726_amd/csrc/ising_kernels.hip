@@ -704,9 +704,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
     const TileLane tl = tile_lane<2>(a);
     uint32_t anti = 0, up = 0;
     if (a.g.nb_last == 64)
-      process_tile_direct<true, 2, true>(a, tl, C, em, ft.local, anti, up);
+      process_tile_direct<true, 2, false>(a, tl, C, em, ft.local, anti, up);
     else
-      process_tile_direct<false, 2, true>(a, tl, C, em, ft.local, anti, up);
+      process_tile_direct<false, 2, false>(a, tl, C, em, ft.local, anti, up);
     if (em) {
       anti = wave_sum(anti);
       up = wave_sum(up);
