@@ -124,6 +124,7 @@ static ising_status run_fused(ising_lattice* const* hs, const std::vector<int>& 
     FusedLattice& F = lat[j];
     std::memset(&F, 0, sizeof(F));
     F.ta = targs[i];
+    make_flat(F.ta);  // the fused kernel loads neighbours directly
     F.ta.t = (uint32_t)hs[i]->sweep;
     F.EM = dev_EM ? dev_EM[i] : nullptr;
     any_em = any_em || F.EM != nullptr;

@@ -419,10 +419,26 @@ __device__ __forceinline__ void process_tile_direct(const TileArgs& a, const Til
   const int32_t w0 = WIDE ? (int32_t)(tidx % a.segs) * 64 : 0;
   const int64_t W = g.W;
   for (int j = 0; j < RPW; ++j) {
-    const int r_l = (wave * RPW + j) * R + tl.r_off;
-    const int64_t y = y0 + r_l;
-    const int32_t w = w0 + tl.w_l;
-    if (!(tl.lane_ok && y < g.L && w < W)) continue;
+    int64_t y;
+    int32_t w;
+    if (a.flat) {
+      const int64_t i = ((tidx * 4 + wave) * RPW + j) * 64 + (threadIdx.x & 63);
+      if (i >= a.plane_words) continue;
+      const uint32_t iu = (uint32_t)i;  // plane_words < 2^32 for flat shapes
+      uint32_t q = (uint32_t)(((uint64_t)iu * a.wdiv_m) >> 32);
+      int64_t r = (int64_t)iu - (int64_t)q * W;
+      if (r < 0) {
+        q -= 1u;
+        r += W;
+      }
+      y = q;
+      w = (int32_t)r;
+    } else {
+      const int r_l = (wave * RPW + j) * R + tl.r_off;
+      y = y0 + r_l;
+      w = w0 + tl.w_l;
+      if (!(tl.lane_ok && y < g.L && w < W)) continue;
+    }
     const int64_t ym = y == 0 ? g.L - 1 : y - 1;
     const int64_t yp = y == g.L - 1 ? 0 : y + 1;
     // horizontal partner: left (site k-1) when (y + colour) is even, else right
@@ -843,6 +859,16 @@ hipError_t launch_lcg_seed(hipStream_t st, uint32_t* state, int64_t n, uint32_t 
   hipLaunchKernelGGL(k_lcg_seed, dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(256), 0, st,
                      state, n, s0);
   return hipGetLastError();
+}
+
+void make_flat(TileArgs& a) {
+  const int64_t W = a.g.W;
+  const int64_t words = a.plane_words;
+  if (64 % W == 0 || W % 64 == 0 || words >= (1ll << 32)) return;
+  a.flat = 1;
+  a.wdiv_m = (uint32_t)((1ull << 32) / (uint64_t)W + 1ull);
+  const int64_t per_tile = 256 * (int64_t)a.RPW;
+  a.tiles = (words + per_tile - 1) / per_tile;
 }
 
 hipError_t launch_strip_sweep(hipStream_t st, int colour, const TileArgs& a, int blocks) {

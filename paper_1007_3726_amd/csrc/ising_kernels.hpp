@@ -59,7 +59,19 @@ struct TileArgs {
   // z < l4m and z + le < l8m (see ising_device.hpp)
   uint32_t* lcg;
   uint32_t l4d, lc, le, l4m, l8m;
+  // flat lane mapping of the direct-load kernels (rows whose width W neither
+  // divides 64 nor is a multiple of it): wave task k covers words
+  // 64 k .. 64 k + 63 of the colour plane in row-major order, so every lane
+  // has a word; tiles = ceil(plane_words / (256 RPW)).  Row of word i:
+  // q = (i * wdiv_m) >> 32 with wdiv_m = floor(2^32 / W) + 1, minus one when
+  // q W > i.
+  int32_t flat;
+  uint32_t wdiv_m;
 };
+
+// Switch tile arguments of a lattice to the flat mapping when its rows need
+// it (see TileArgs::flat); keeps RPW.
+void make_flat(TileArgs& a);
 
 hipError_t launch_tile_sweep(hipStream_t st, int colour, const TileArgs& a, int blocks);
 // Strip form (W >= kWideMinWords): TileArgs with TW = 64, R = 1, RPW = rows

@@ -205,6 +205,7 @@ ising_status enqueue_sweeps(ising_lattice* h, int64_t n, int64_t* dev_EM) {
   TileArgs ta;
   const bool strip = strip_args(h, &ta);
   if (strip || tile_args(h, &ta)) {
+    if (!strip) make_flat(ta);  // direct-load tiles: every lane busy at any W
     const int64_t units = strip ? (ta.tiles + 3) / 4 : ta.tiles;  // 4 wave tasks per block
     const int blocks = (int)std::min<int64_t>(units, std::min(h->tune.max_blocks,
                                                               kMaxSweepBlocks));

@@ -127,3 +127,24 @@ def test_batched_rows_of_62_to_64_words(I, form):
     specs = [(7936, 2.3, 1, 1, H), (8000, 2.4, 2, 2, H), (8064, 2.5, 3, 3, H), (96, 2.0, 4, 4, H)]
     _say("case batched W=62..63 form=%s" % form)
     _batched_vs_plain(I, specs, 2, form=form)
+
+
+def test_lattice_totals_past_2_to_the_32(I):
+    """L = 65536 from a cold start: N = 2^32 up spins, so the per-lattice
+    up-spin and bond totals of the fused finaliser need 64 bits.  Batched
+    per-sweep E/M equal the plain path's (64-bit per-block partials); spins
+    compared on windows (the full lattice is 4 GiB as int8)."""
+    import torch
+    L, n = 65536, 2
+    spec = [(L, 2.0, 3, 1, workloads.INIT_COLD_UP)]
+    _say("case L=%d fused" % L)
+    b = _make(I, spec)[0]
+    EMb = torch.empty((n, 2), dtype=torch.int64, device="cuda")
+    I.multi_sweep([b], n, [EMb], form="fused")
+    EMb = EMb.cpu().numpy()
+    p = _make(I, spec)[0]
+    EMp = p.sweep_em(n).cpu().numpy()
+    assert np.array_equal(EMb, EMp)
+    assert EMp[-1, 1] > (1 << 31)  # most spins still up: the total exceeds 2^32 / 2
+    for (x0, y0) in [(0, 0), (L - 40, L - 7), (L // 2, 12345)]:
+        assert np.array_equal(b.get_window(x0, y0, 64, 16), p.get_window(x0, y0, 64, 16))
