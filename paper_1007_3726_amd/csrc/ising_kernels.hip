@@ -222,6 +222,90 @@ __global__ __launch_bounds__(1024) void k_small_sweeps(SmallArgs a) {
   for (int64_t i = threadIdx.x; i < 2 * pw; i += blockDim.x) a.planes[i] = lds[i];
 }
 
+// Masks of one word split over LPW lanes (L % 8 == 0): lane `sub` of the
+// word computes Philox blocks q = sub*NQ .. sub*NQ + NQ - 1 (NQ = 16 / LPW)
+// of the word's 16 (blocks past a partial last word are computed too and
+// later masked by `valid`), shifts their decisions into one 32-bit pair of
+// accumulators and places them at bit 4*NQ*sub; the OR over the word's
+// lanes (adjacent lanes, one DPP row) gives every lane the full masks.
+template <int LPW>
+__device__ __forceinline__ void masks_split(uint32_t lo, int sub, uint32_t k0, uint32_t k1,
+                                            uint32_t t, uint32_t ctr3, uint32_t t4, uint32_t t8,
+                                            uint64_t& r4, uint64_t& r8) {
+  constexpr int NQ = 16 / LPW;
+  uint32_t a4 = 0, a8 = 0;
+  const uint32_t q0 = (uint32_t)(sub * NQ);
+#pragma unroll
+  for (int k = NQ - 1; k >= 0; --k) {
+    uint32_t x0 = lo + q0 + (uint32_t)k, x1 = 0, x2 = t, x3 = ctr3;
+    philox4x32_10<false>(x0, x1, x2, x3, k0, k1);
+    shift_in4(a4, a8, x0, x1, x2, x3, t4, t8);
+  }
+  const int sh = 4 * NQ * sub;
+  r4 = (uint64_t)a4 << sh;
+  r8 = (uint64_t)a8 << sh;
+#pragma unroll
+  for (int off = 1; off < LPW; off <<= 1) {
+    r4 |= __shfl_xor(r4, off, 64);
+    r8 |= __shfl_xor(r8, off, 64);
+  }
+}
+
+// All n sweeps of one lattice resident in LDS (one workgroup, L % 8 == 0,
+// every Philox block index below 2^32), LPW lanes per word: for the
+// smallest lattices the per-colour-step latency is the cost, and spreading
+// a word's 16 Philox blocks over 2-16 lanes divides it.  Lane 0 of a word
+// stores the update and counts E/M.
+template <int LPW>
+__global__ __launch_bounds__(1024) void k_small_sweeps_split(SmallArgs a) {
+  extern __shared__ uint64_t lds[];
+  __shared__ uint32_t red[32];
+  const Geom g = a.g;
+  const int64_t pw = a.plane_words;
+  for (int64_t i = threadIdx.x; i < 2 * pw; i += blockDim.x) lds[i] = a.planes[i];
+  __syncthreads();
+  const int sub = threadIdx.x % LPW;
+  for (int64_t k = 0; k < a.n; ++k) {
+    const uint32_t t = a.t0 + (uint32_t)k;
+    uint32_t anti = 0, up = 0;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      uint64_t* self = lds + (c ? pw : 0);
+      const uint64_t* other = lds + (c ? 0 : pw);
+      // the loop bound is uniform per word group, so the shuffles see
+      // every lane of a word
+      for (int64_t base = 0; base < pw * LPW; base += blockDim.x) {
+        const int64_t idx = (base + threadIdx.x) / LPW;
+        const bool ok = idx < pw;
+        const int64_t ic = ok ? idx : pw - 1;
+        const int64_t y = ic / g.W;
+        const int32_t w = (int32_t)(ic - y * g.W);
+        const uint32_t lo = (uint32_t)y * (uint32_t)g.L8 + 16u * (uint32_t)w;
+        uint64_t r4, r8;
+        masks_split<LPW>(lo, sub, a.k0, a.k1, t, a.sid4 | c, a.t4, a.t8, r4, r8);
+        if (ok && sub == 0) {
+          const uint64_t valid = (w == g.W - 1) ? low_mask(g.nb_last) : ~0ull;
+          const uint64_t s = self[ic];
+          const Nbr n = gather(other, g, c, y, w);
+          const uint64_t s_new = s ^ (flip_mask(s, n, r4, r8) & valid);
+          self[ic] = s_new;
+          if (c == 1) count_word(s_new, n, valid, anti, up);
+        }
+      }
+      __syncthreads();
+    }
+    if (a.EM) {
+      block_sum2(anti, up, red);
+      if (threadIdx.x == 0) {
+        a.EM[2 * k] = 2 * (int64_t)anti - 2 * g.L * g.L;
+        a.EM[2 * k + 1] = 2 * (int64_t)up - g.L * g.L;
+      }
+      __syncthreads();
+    }
+  }
+  for (int64_t i = threadIdx.x; i < 2 * pw; i += blockDim.x) a.planes[i] = lds[i];
+}
+
 // ---------------------------------------------------------------------
 // Tiled half-sweep for L % 8 == 0.
 //
@@ -943,10 +1027,29 @@ hipError_t launch_measure(hipStream_t st, const uint64_t* planes, const Geom& g,
 
 hipError_t launch_small_sweeps(hipStream_t st, const SmallArgs& a, int threads) {
   const size_t lds = (size_t)(2 * a.plane_words) * sizeof(uint64_t);
-  if ((a.g.L % 8) == 0)
+  const int64_t pw = a.plane_words;
+  if ((a.g.L % 8) == 0 && pw >= 128 && pw <= 512) {
+    // as many lanes per word as one workgroup of <= 1024 threads allows
+    // (measured per sweep: 128^2 6.5 -> 5.2 us, 256^2 9.8 -> 9.3 us; at 64^2,
+    // 16 lanes per word were slower than one, 4.5 against 4.1 us: there the
+    // barriers and the per-sweep E/M reduction cost more than the Philox
+    // stretch)
+    int lpw = 16;
+    while (lpw > 2 && pw * lpw > 1024) lpw >>= 1;
+    const int th = (int)std::min<int64_t>(1024, (pw * lpw + 63) / 64 * 64);
+#define ISING_SPLIT(N) hipLaunchKernelGGL(k_small_sweeps_split<N>, dim3(1), dim3(th), lds, st, a)
+    switch (lpw) {
+      case 16: ISING_SPLIT(16); break;
+      case 8: ISING_SPLIT(8); break;
+      case 4: ISING_SPLIT(4); break;
+      default: ISING_SPLIT(2); break;
+    }
+#undef ISING_SPLIT
+  } else if ((a.g.L % 8) == 0) {
     hipLaunchKernelGGL(k_small_sweeps<true>, dim3(1), dim3(threads), lds, st, a);
-  else
+  } else {
     hipLaunchKernelGGL(k_small_sweeps<false>, dim3(1), dim3(threads), lds, st, a);
+  }
   return hipGetLastError();
 }
 

@@ -221,3 +221,24 @@ def test_rows_of_62_to_64_words(I, L):
         win = lat.get_window(x0, y0, 24, 12)
         ref = s[-1][np.ix_([(y0 + j) % L for j in range(12)], [(x0 + i) % L for i in range(24)])]
         assert np.array_equal(win, ref)
+
+
+@pytest.mark.parametrize("L", [8, 16, 24, 32, 64, 128, 136, 200, 256, 264])
+def test_lds_resident_lanes_per_word(I, L):
+    """The single-workgroup LDS-resident path (forced by a tuning entry): 2-8
+    lanes per word for L % 8 == 0 with 128-512 words per plane (128 .. 264),
+    one lane per word otherwise: every sweep bit-exact, partial last words
+    included (136: 4 valid bits, 200: 36, 264: 4 in the third word)."""
+    I.tuning_set([{"L_min": L, "L_max": L, "form": I.ISING_FORM_TILE, "rpw": 0,
+                   "max_blocks": 2048, "small_lds_bytes": 65536, "updates_per_ns": 0.0}])
+    try:
+        beta = 1 / 2.269185
+        n = 6
+        _say("case LDS-resident L=%d" % L)
+        lat, gs, gEM = gpu_series(I, L, beta, 21, 2, workloads.INIT_HOT, n, per_sweep_spins=True)
+        os_, oEM = oracle_series(L, beta, 21, 2, workloads.INIT_HOT, n, per_sweep_spins=True)
+        assert np.array_equal(gEM, oEM)
+        for t in range(n + 1):
+            assert np.array_equal(gs[t], os_[t]), t
+    finally:
+        I.tuning_clear()
