@@ -11,7 +11,7 @@ Also reported on the same JSON line:
   cpu_baseline  - the CPU oracle timed on a bounded sample of the same
                   workload on this host's cores (a baseline, not the target).
 
-Usage: python bench.py [--gpus 1] [--steps 3] [--warmup 1]
+Usage: python bench.py [--gpus 1] [--steps 5] [--warmup 1]
 """
 import argparse
 import json
@@ -38,10 +38,10 @@ ALU_OPS_PER_UPDATE = 14.0
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=3)
+    p.add_argument("--steps", type=int, default=5)
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--cpu-sweeps", type=int, default=4,
+    p.add_argument("--cpu-sweeps", type=int, default=16,
                    help="sweeps of the 16384^2 lattice the oracle runs for the CPU baseline")
     p.add_argument("--sweeps", type=int, default=None,
                    help="sweeps per step (default: the workload's 2000); for short profiles")
