@@ -124,7 +124,7 @@ static ising_status run_fused(ising_lattice* const* hs, const std::vector<int>& 
     FusedLattice& F = lat[j];
     std::memset(&F, 0, sizeof(F));
     F.ta = targs[i];
-    make_flat(F.ta);  // the fused kernel loads neighbours directly
+    make_flat(F.ta, true);  // the fused kernel uses the flat mapping for every lattice
     F.ta.t = (uint32_t)hs[i]->sweep;
     F.EM = dev_EM ? dev_EM[i] : nullptr;
     any_em = any_em || F.EM != nullptr;
@@ -263,7 +263,9 @@ ising_status batch_sweeps(ising_lattice* const* hs, int32_t count, int64_t n,
   std::vector<TileArgs> targs(count);
   for (int i = 0; i < count; ++i) {
     TileArgs ta;
-    if (tile_args(hs[i], &ta)) {
+    // the fused kernel indexes a plane with 32-bit word numbers: planes of
+    // 2^32 words or more (L >= 741456) take the plain path
+    if (tile_args(hs[i], &ta) && hs[i]->plane_words < (1ll << 32)) {
       // fine tiles balance best across the flat list; lattices with many
       // tiles take two row groups per wave (less staging per word)
       ta.RPW = 1;

@@ -488,7 +488,7 @@ __device__ __forceinline__ void process_tile(const TileArgs& a, const TileLane& 
 // shared by neighbouring lanes hit in L1/L2), issues the loads before the
 // Philox stretch and uses them after it.  No block barrier: the four waves
 // of a workgroup work independently.
-template <bool FULL, int WIDEM, bool BUMP_SALU = false, bool LCG = false>
+template <bool FULL, int WIDEM, bool BUMP_SALU = false, bool LCG = false, bool FLAT = false>
 __device__ __forceinline__ void process_tile_direct(const TileArgs& a, const TileLane& tl,
                                                     int colour, bool em, int64_t tidx,
                                                     uint32_t& anti, uint32_t& up) {
@@ -505,18 +505,23 @@ __device__ __forceinline__ void process_tile_direct(const TileArgs& a, const Til
   for (int j = 0; j < RPW; ++j) {
     int64_t y;
     int32_t w;
-    if (a.flat) {
+    if (FLAT) {
       const int64_t i = ((tidx * 4 + wave) * RPW + j) * 64 + (threadIdx.x & 63);
       if (i >= a.plane_words) continue;
       const uint32_t iu = (uint32_t)i;  // plane_words < 2^32 for flat shapes
-      uint32_t q = (uint32_t)(((uint64_t)iu * a.wdiv_m) >> 32);
-      int64_t r = (int64_t)iu - (int64_t)q * W;
-      if (r < 0) {
-        q -= 1u;
-        r += W;
+      if (W == 1) {  // floor(2^32 / 1) + 1 does not fit 32 bits
+        y = iu;
+        w = 0;
+      } else {
+        uint32_t q = (uint32_t)(((uint64_t)iu * a.wdiv_m) >> 32);
+        int64_t r = (int64_t)iu - (int64_t)q * W;
+        if (r < 0) {
+          q -= 1u;
+          r += W;
+        }
+        y = q;
+        w = (int32_t)r;
       }
-      y = q;
-      w = (int32_t)r;
     } else {
       const int r_l = (wave * RPW + j) * R + tl.r_off;
       y = y0 + r_l;
@@ -575,7 +580,7 @@ __device__ __forceinline__ void process_tile_direct(const TileArgs& a, const Til
 
 // Tiles read their neighbour words directly (process_tile_direct): no LDS
 // staging and no barrier until the E/M reduction at the end.
-template <int C, bool EM, bool FULL, bool WIDE, bool LCG>
+template <int C, bool EM, bool FULL, bool WIDE, bool LCG, bool FLAT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_tile_sweep(
     TileArgs a) {
   __shared__ uint64_t red64[8];
@@ -589,7 +594,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
   uint32_t anti = 0, up = 0;
   const TileLane tl = tile_lane<WIDE ? 1 : 0>(a);
   for (int64_t tidx = lb; tidx < a.tiles; tidx += G)
-    process_tile_direct<FULL, WIDE ? 1 : 0, false, LCG>(a, tl, C, EM, tidx, anti, up);
+    process_tile_direct<FULL, WIDE ? 1 : 0, false, LCG, FLAT>(a, tl, C, EM, tidx, anti, up);
   if (C == 1 && EM) {
     block_sum2(anti, up, red);
     if (threadIdx.x == 0) {
@@ -803,10 +808,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
     const bool em = C == 1 && Lt.EM != nullptr;
     const TileLane tl = tile_lane<2>(a);
     uint32_t anti = 0, up = 0;
+    // every fused lattice uses the flat mapping (run_fused sets it; for W
+    // dividing 64 it is the narrow mapping itself)
     if (a.g.nb_last == 64)
-      process_tile_direct<true, 2, false>(a, tl, C, em, ft.local, anti, up);
+      process_tile_direct<true, 2, false, false, true>(a, tl, C, em, ft.local, anti, up);
     else
-      process_tile_direct<false, 2, false>(a, tl, C, em, ft.local, anti, up);
+      process_tile_direct<false, 2, false, false, true>(a, tl, C, em, ft.local, anti, up);
     if (em) {
       anti = wave_sum(anti);
       up = wave_sum(up);
@@ -890,13 +897,14 @@ hipError_t launch_advance(hipStream_t st, uint32_t* kbase, uint32_t by) {
 // ---------------------------------------------------------------------
 // Host-side launchers
 // ---------------------------------------------------------------------
-template <bool LCG>
+template <bool LCG, bool FLAT>
 static void launch_tile_sweep_rng(hipStream_t st, int colour, const TileArgs& a, int blocks) {
   const bool em = (colour == 1) ? (a.part != nullptr) : false;
   const bool full = a.g.nb_last == 64;
-  const bool wide = a.g.W >= kWideMinWords;
+  // the flat mapping does not use the row-group shape: one instantiation
+  const bool wide = !FLAT && a.g.W >= kWideMinWords;
 #define ISING_TILE(C, E, F, WI) \
-  hipLaunchKernelGGL((k_tile_sweep<C, E, F, WI, LCG>), dim3(blocks), dim3(256), 0, st, a)
+  hipLaunchKernelGGL((k_tile_sweep<C, E, F, WI, LCG, FLAT>), dim3(blocks), dim3(256), 0, st, a)
 #define ISING_TILE_FW(C, E)                                   \
   do {                                                        \
     if (full) {                                               \
@@ -918,10 +926,17 @@ static void launch_tile_sweep_rng(hipStream_t st, int colour, const TileArgs& a,
 }
 
 hipError_t launch_tile_sweep(hipStream_t st, int colour, const TileArgs& a, int blocks) {
-  if (a.lcg)
-    launch_tile_sweep_rng<true>(st, colour, a, blocks);
-  else
-    launch_tile_sweep_rng<false>(st, colour, a, blocks);
+  if (a.lcg) {
+    if (a.flat)
+      launch_tile_sweep_rng<true, true>(st, colour, a, blocks);
+    else
+      launch_tile_sweep_rng<true, false>(st, colour, a, blocks);
+  } else {
+    if (a.flat)
+      launch_tile_sweep_rng<false, true>(st, colour, a, blocks);
+    else
+      launch_tile_sweep_rng<false, false>(st, colour, a, blocks);
+  }
   return hipGetLastError();
 }
 
@@ -945,12 +960,13 @@ hipError_t launch_lcg_seed(hipStream_t st, uint32_t* state, int64_t n, uint32_t 
   return hipGetLastError();
 }
 
-void make_flat(TileArgs& a) {
+void make_flat(TileArgs& a, bool always) {
   const int64_t W = a.g.W;
   const int64_t words = a.plane_words;
-  if (64 % W == 0 || W % 64 == 0 || words >= (1ll << 32)) return;
+  if (words >= (1ll << 32)) return;
+  if (!always && (64 % W == 0 || W % 64 == 0)) return;
   a.flat = 1;
-  a.wdiv_m = (uint32_t)((1ull << 32) / (uint64_t)W + 1ull);
+  a.wdiv_m = W == 1 ? 0u : (uint32_t)((1ull << 32) / (uint64_t)W + 1ull);
   const int64_t per_tile = 256 * (int64_t)a.RPW;
   a.tiles = (words + per_tile - 1) / per_tile;
 }

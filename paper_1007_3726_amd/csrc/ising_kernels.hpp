@@ -69,9 +69,11 @@ struct TileArgs {
   uint32_t wdiv_m;
 };
 
-// Switch tile arguments of a lattice to the flat mapping when its rows need
-// it (see TileArgs::flat); keeps RPW.
-void make_flat(TileArgs& a);
+// Switch tile arguments of a lattice to the flat mapping (see
+// TileArgs::flat) when its rows need it, or for any row width with
+// `always`; keeps RPW.  Lattices of 2^32 or more words per plane keep the
+// row-group mapping.
+void make_flat(TileArgs& a, bool always = false);
 
 hipError_t launch_tile_sweep(hipStream_t st, int colour, const TileArgs& a, int blocks);
 // Strip form (W >= kWideMinWords): TileArgs with TW = 64, R = 1, RPW = rows
