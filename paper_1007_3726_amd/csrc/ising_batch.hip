@@ -48,7 +48,7 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 ising_status ensure_table(DeviceTable& T, size_t bytes) {
   if (T.cap >= bytes) return ISING_OK;
-  if (T.ptr) hipFree(T.ptr);
+  if (T.ptr) (void)hipFree(T.ptr);
   T.ptr = nullptr;
   T.cap = 0;
   const size_t want = std::max<size_t>(bytes * 2, 1 << 20);
@@ -186,8 +186,8 @@ static ising_status run_fused(ising_lattice* const* hs, const std::vector<int>& 
     for (int64_t r = 0; r < reps && e == hipSuccess; ++r) e = hipGraphLaunch(exec, stream);
     // the executable graph may be destroyed once its launches are enqueued
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
-    if (exec) hipGraphExecDestroy(exec);
-    if (graph) hipGraphDestroy(graph);
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
     if (e != hipSuccess) return hip_fail(e, "batched sweeps: graph capture/replay");
     done = reps * K;
   }

@@ -487,7 +487,7 @@ __device__ __forceinline__ void process_tile(const TileArgs& a, const TileLane& 
 // own word and its four neighbour words straight from memory (the rows
 // shared by neighbouring lanes hit in L1/L2), issues the loads before the
 // Philox stretch and uses them after it.  No block barrier: the four waves
-// of a workgroup work independently.
+// of a workgroup work independently.  Spin words are stored write-through.
 template <bool FULL, int WIDEM, bool BUMP_SALU = false, bool LCG = false, bool FLAT = false>
 __device__ __forceinline__ void process_tile_direct(const TileArgs& a, const TileLane& tl,
                                                     int colour, bool em, int64_t tidx,
@@ -573,7 +573,9 @@ __device__ __forceinline__ void process_tile_direct(const TileArgs& a, const Til
     }
     const uint64_t valid = (FULL || w < W - 1) ? ~0ull : low_mask(g.nb_last);
     const uint64_t s_new = s ^ (flip_mask(s, n, r4, r8) & valid);
-    self[y * W + w] = s_new;
+    // write-through at device scope (sc1): the XCD L2s then hold no dirty
+    // lattice lines for the write-back at the end of the launch
+    __hip_atomic_store(&self[y * W + w], s_new, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (colour == 1 && em) count_word(s_new, n, valid, anti, up);
   }
 }

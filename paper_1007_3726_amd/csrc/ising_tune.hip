@@ -129,8 +129,8 @@ ising_status ising_autotune(int64_t L, void* dev_buf, size_t dev_bytes, void* hi
       best_t = cands[i].t;
     }
   }
-  if (a) hipEventDestroy(a);
-  if (b) hipEventDestroy(b);
+  if (a) (void)hipEventDestroy(a);
+  if (b) (void)hipEventDestroy(b);
   ising_destroy(h);
   if (st != ISING_OK) return st;
   if (e != hipSuccess) return hip_fail(e, "ising_autotune: timing");
