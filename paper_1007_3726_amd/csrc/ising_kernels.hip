@@ -28,11 +28,18 @@ __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
   return v;
 }
 
-// Sum (a, p) over the block; thread 0 gets the totals.  `red` holds 2
+// Sum (a, p) over the block in 64 bits (a block of a large lattice can
+// count more than 2^32 bonds); thread 0 gets the totals.  `red` holds 2
 // entries per wave.
-__device__ __forceinline__ void block_sum2(uint32_t& a, uint32_t& p, uint32_t* red) {
-  a = wave_sum(a);
-  p = wave_sum(p);
+__device__ __forceinline__ void block_sum2(uint32_t a32, uint32_t p32, uint64_t* red, uint64_t& a,
+                                           uint64_t& p) {
+  a = a32;
+  p = p32;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    a += __shfl_xor(a, off, 64);
+    p += __shfl_xor(p, off, 64);
+  }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if (lane == 0) {
     red[2 * wave] = a;
@@ -46,8 +53,8 @@ __device__ __forceinline__ void block_sum2(uint32_t& a, uint32_t& p, uint32_t* r
       sa += red[2 * i];
       sp += red[2 * i + 1];
     }
-    a = (uint32_t)sa;
-    p = (uint32_t)sp;
+    a = sa;
+    p = sp;
   }
 }
 
@@ -106,7 +113,7 @@ __global__ __launch_bounds__(256) void k_init(uint64_t* __restrict__ planes, Geo
 // ---------------------------------------------------------------------
 template <int C, bool ALIGNED, bool EM>
 __global__ __launch_bounds__(256) void k_half_sweep(SweepArgs a) {
-  __shared__ uint32_t red[2 * 16];
+  __shared__ uint64_t red[2 * 16];
   const Geom g = a.g;
   uint64_t* __restrict__ self = a.planes + (C ? a.plane_words : 0);
   const uint64_t* __restrict__ other = a.planes + (C ? 0 : a.plane_words);
@@ -133,10 +140,11 @@ __global__ __launch_bounds__(256) void k_half_sweep(SweepArgs a) {
     if (C == 1 && EM) count_word(s_new, n, valid, anti, up);
   }
   if (C == 1 && EM) {
-    block_sum2(anti, up, red);
+    uint64_t sa, sp;
+    block_sum2(anti, up, red, sa, sp);
     if (threadIdx.x == 0) {
-      atomicAdd((unsigned long long*)&a.EM[0], (unsigned long long)(2ull * anti));
-      atomicAdd((unsigned long long*)&a.EM[1], (unsigned long long)(2ull * up));
+      atomicAdd((unsigned long long*)&a.EM[0], (unsigned long long)(2ull * sa));
+      atomicAdd((unsigned long long*)&a.EM[1], (unsigned long long)(2ull * sp));
     }
   }
 }
@@ -147,7 +155,7 @@ __global__ __launch_bounds__(256) void k_half_sweep(SweepArgs a) {
 // ---------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_measure(const uint64_t* __restrict__ planes, Geom g,
                                                  int64_t plane_words, int64_t* EM) {
-  __shared__ uint32_t red[2 * 16];
+  __shared__ uint64_t red[2 * 16];
   const uint64_t* self = planes + plane_words;
   const uint64_t* other = planes;
   uint32_t anti = 0, up = 0;
@@ -159,10 +167,11 @@ __global__ __launch_bounds__(256) void k_measure(const uint64_t* __restrict__ pl
     const Nbr n = gather(other, g, 1, y, w);
     count_word(self[idx], n, valid, anti, up);
   }
-  block_sum2(anti, up, red);
+  uint64_t sa, sp;
+  block_sum2(anti, up, red, sa, sp);
   if (threadIdx.x == 0) {
-    atomicAdd((unsigned long long*)&EM[0], (unsigned long long)(2ull * anti));
-    atomicAdd((unsigned long long*)&EM[1], (unsigned long long)(2ull * up));
+    atomicAdd((unsigned long long*)&EM[0], (unsigned long long)(2ull * sa));
+    atomicAdd((unsigned long long*)&EM[1], (unsigned long long)(2ull * sp));
   }
 }
 
@@ -181,7 +190,7 @@ __global__ void k_set_em(int64_t* EM, int64_t e, int64_t m) {
 template <bool ALIGNED>
 __global__ __launch_bounds__(1024) void k_small_sweeps(SmallArgs a) {
   extern __shared__ uint64_t lds[];
-  __shared__ uint32_t red[2 * 16];
+  __shared__ uint64_t red[2 * 16];
   const Geom g = a.g;
   const int64_t pw = a.plane_words;
   for (int64_t i = threadIdx.x; i < 2 * pw; i += blockDim.x) lds[i] = a.planes[i];
@@ -211,10 +220,11 @@ __global__ __launch_bounds__(1024) void k_small_sweeps(SmallArgs a) {
       __syncthreads();
     }
     if (a.EM) {
-      block_sum2(anti, up, red);
+      uint64_t sa, sp;
+      block_sum2(anti, up, red, sa, sp);
       if (threadIdx.x == 0) {
-        a.EM[2 * k] = 2 * (int64_t)anti - 2 * g.L * g.L;
-        a.EM[2 * k + 1] = 2 * (int64_t)up - g.L * g.L;
+        a.EM[2 * k] = 2 * (int64_t)sa - 2 * g.L * g.L;
+        a.EM[2 * k + 1] = 2 * (int64_t)sp - g.L * g.L;
       }
       __syncthreads();
     }
@@ -259,7 +269,7 @@ __device__ __forceinline__ void masks_split(uint32_t lo, int sub, uint32_t k0, u
 template <int LPW>
 __global__ __launch_bounds__(1024) void k_small_sweeps_split(SmallArgs a) {
   extern __shared__ uint64_t lds[];
-  __shared__ uint32_t red[32];
+  __shared__ uint64_t red[32];
   const Geom g = a.g;
   const int64_t pw = a.plane_words;
   for (int64_t i = threadIdx.x; i < 2 * pw; i += blockDim.x) lds[i] = a.planes[i];
@@ -295,10 +305,11 @@ __global__ __launch_bounds__(1024) void k_small_sweeps_split(SmallArgs a) {
       __syncthreads();
     }
     if (a.EM) {
-      block_sum2(anti, up, red);
+      uint64_t sa, sp;
+      block_sum2(anti, up, red, sa, sp);
       if (threadIdx.x == 0) {
-        a.EM[2 * k] = 2 * (int64_t)anti - 2 * g.L * g.L;
-        a.EM[2 * k + 1] = 2 * (int64_t)up - g.L * g.L;
+        a.EM[2 * k] = 2 * (int64_t)sa - 2 * g.L * g.L;
+        a.EM[2 * k + 1] = 2 * (int64_t)sp - g.L * g.L;
       }
       __syncthreads();
     }
@@ -586,7 +597,7 @@ template <int C, bool EM, bool FULL, bool WIDE, bool LCG, bool FLAT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_tile_sweep(
     TileArgs a) {
   __shared__ uint64_t red64[8];
-  __shared__ uint32_t red[8];
+  __shared__ uint64_t red[8];
   if (C == 0 && a.prev_EM != nullptr && blockIdx.x == 0)
     finalize_partials(a.prev_part, a.prev_blocks, a.g.L, a.prev_EM, red64);
   // logical block number grouped by XCD
@@ -598,10 +609,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
   for (int64_t tidx = lb; tidx < a.tiles; tidx += G)
     process_tile_direct<FULL, WIDE ? 1 : 0, false, LCG, FLAT>(a, tl, C, EM, tidx, anti, up);
   if (C == 1 && EM) {
-    block_sum2(anti, up, red);
+    uint64_t sa, sp;
+    block_sum2(anti, up, red, sa, sp);
     if (threadIdx.x == 0) {
-      a.part[2 * blockIdx.x] = anti;
-      a.part[2 * blockIdx.x + 1] = up;
+      a.part[2 * blockIdx.x] = sa;
+      a.part[2 * blockIdx.x + 1] = sp;
     }
   }
 }
@@ -706,7 +718,7 @@ template <int C, bool EM, bool FULL>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_strip_sweep(
     TileArgs a) {
   __shared__ uint64_t red64[8];
-  __shared__ uint32_t red[8];
+  __shared__ uint64_t red[8];
   if (C == 0 && a.prev_EM != nullptr && blockIdx.x == 0)
     finalize_partials(a.prev_part, a.prev_blocks, a.g.L, a.prev_EM, red64);
   // logical block number grouped by XCD, so that neighbouring tasks share an L2
@@ -718,10 +730,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
   for (int64_t task = (int64_t)lb * 4 + wave; task < a.tiles; task += (int64_t)G * 4)
     strip_task<C, EM, FULL>(a, task, anti, up);
   if (C == 1 && EM) {
-    block_sum2(anti, up, red);
+    uint64_t sa, sp;
+    block_sum2(anti, up, red, sa, sp);
     if (threadIdx.x == 0) {
-      a.part[2 * blockIdx.x] = anti;
-      a.part[2 * blockIdx.x + 1] = up;
+      a.part[2 * blockIdx.x] = sa;
+      a.part[2 * blockIdx.x + 1] = sp;
     }
   }
 }
@@ -838,7 +851,7 @@ __global__ void k_advance(uint32_t* kbase, uint32_t by) {
 }
 
 __device__ __forceinline__ void run_packed_lattice(const BatchLattice& Lt, int64_t n,
-                                                   uint64_t* tile, uint32_t* red) {
+                                                   uint64_t* tile, uint64_t* red) {
   TileArgs a = Lt.ta;
   const uint32_t t0 = Lt.ta.t;
   const bool em = Lt.EM != nullptr;
@@ -852,10 +865,11 @@ __device__ __forceinline__ void run_packed_lattice(const BatchLattice& Lt, int64
     for (int64_t tidx = 0; tidx < a.tiles; ++tidx)
       process_tile<false, 2, true>(a, tl, 1, em, tidx, tile, anti, up);
     if (em) {
-      block_sum2(anti, up, red);
+      uint64_t sa, sp;
+      block_sum2(anti, up, red, sa, sp);
       if (threadIdx.x == 0) {
-        Lt.EM[2 * k] = 2 * (int64_t)anti - 2 * a.g.L * a.g.L;
-        Lt.EM[2 * k + 1] = 2 * (int64_t)up - a.g.L * a.g.L;
+        Lt.EM[2 * k] = 2 * (int64_t)sa - 2 * a.g.L * a.g.L;
+        Lt.EM[2 * k + 1] = 2 * (int64_t)sp - a.g.L * a.g.L;
       }
       __syncthreads();
     }
@@ -864,7 +878,7 @@ __device__ __forceinline__ void run_packed_lattice(const BatchLattice& Lt, int64
 
 __global__ __launch_bounds__(256) void k_batch(BatchArgs b) {
   __shared__ uint64_t tile[kTileLdsMaxWords];
-  __shared__ uint32_t red[8];
+  __shared__ uint64_t red[8];
   // The tables are read-only for the whole launch: read them through the
   // constant address space so that they land in SGPRs (scalar loads).
   typedef const BatchWG ISING_CONSTANT_AS* WgPtr;

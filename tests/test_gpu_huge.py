@@ -58,3 +58,48 @@ def test_huge_lattice_windows(I, w, n):
         ref = oracle.window(L, 1.0 / w.T, w.seed, w.stream_id, w.init, 0, n, x0, y0, ww, hh)
         assert np.array_equal(got, ref), "window at (%d, %d) differs" % (x0, y0)
     del lat
+
+
+def _windows_and_invariants(I, L, T, seed, n, spots):
+    lat = I.Lattice(L, seed=seed, stream_id=0, init=workloads.INIT_HOT, beta=1.0 / T)
+    EM = lat.sweep_em(n).cpu().numpy()
+    N = L * L
+    assert np.all(EM[:, 0] % 4 == 0) and np.all((EM[:, 1] - N) % 2 == 0)
+    assert np.all(np.abs(EM[:, 0]) <= 2 * N) and np.all(np.abs(EM[:, 1]) <= N)
+    assert lat.measure() == (int(EM[-1, 0]), int(EM[-1, 1]))
+    ww, hh = 40, 12
+    for (x0, y0) in spots:
+        got = lat.get_window(x0, y0, ww, hh)
+        ref = oracle.window(L, 1.0 / T, seed, 0, workloads.INIT_HOT, 0, n, x0, y0, ww, hh)
+        assert np.array_equal(got, ref), "window at (%d, %d) differs" % (x0, y0)
+    del lat
+
+
+def test_largest_lattice_that_fits(I):
+    """1048576^2 (128 GiB packed): each colour plane holds 2^33 words, so
+    word indices, tile counts and per-block bond counts pass 32 bits, and
+    Philox block indices reach 2^37."""
+    import torch
+    if torch.cuda.get_device_properties(0).total_memory < 160 * (1 << 30):
+        pytest.skip("needs > 160 GiB of device memory")
+    L = 1 << 20
+    assert L * (L // 128) >= 1 << 32
+    _say("case L=%d" % L)
+    spots = [(0, 0), (L - 20, L - 5), (L - 7, 1000), (777777, L - 3), (L // 2, L // 2)]
+    _windows_and_invariants(I, L, 2.0, 7, 3, spots)
+    torch.cuda.empty_cache()
+
+
+def test_non_power_of_two_past_2_to_the_32_blocks(I):
+    """185368^2: more than 2^32 Philox blocks per colour and L not a power
+    of two, so rows straddle a change of the counter's high word (the
+    general colour-step kernel serves this shape)."""
+    import torch
+    L = 185368
+    assert L % 8 == 0 and L * L // 8 > 1 << 32 and L & (L - 1)
+    _say("case L=%d" % L)
+    # the first row whose block indices straddle 2^32: y L/8 < 2^32 < (y+1) L/8
+    ys = (1 << 32) // (L // 8)
+    spots = [(0, 0), (L - 20, L - 5), (L - 30, ys - 4), (5000, ys - 2), (L // 2, L // 2)]
+    _windows_and_invariants(I, L, 2.269185, 11, 4, spots)
+    torch.cuda.empty_cache()
