@@ -9,7 +9,11 @@ updates per ns (N * sweeps / time).
 Also reported on the same JSON line:
   roofline      - the half-sweep kernel against the integer VALU issue peak;
   cpu_baseline  - the CPU oracle timed on a bounded sample of the same
-                  workload on this host's cores (a baseline, not the target).
+                  workload on this host's cores (a baseline, not the target);
+  cpu_msc       - the multi-spin-coded CPU baseline (same chain, 64 spins per
+                  word, vectorised Philox) on the same workload, all cores and
+                  one core: the kind of CPU program the paper's speed-ups are
+                  stated against.
 
 Usage: python bench.py [--gpus 1] [--steps 5] [--warmup 1]
 """
@@ -55,6 +59,8 @@ def parse():
                    help="plain workload: large = 16384^2 (the headline), huge = 262144^2 "
                         "(8 GiB, HBM-resident), small = 64^2, paper-4096 = 4096^2 at 0.99 T_c")
     p.add_argument("--no-served", action="store_true", help="skip the served request stream")
+    p.add_argument("--no-cpu-msc", action="store_true",
+                   help="skip the multi-spin-coded CPU baseline")
     p.add_argument("--no-lcg", action="store_true",
                    help="skip the plain workload with the paper's LCG random numbers")
     p.add_argument("--no-autotune", action="store_true",
@@ -366,6 +372,46 @@ def bench_fss_proof(torch, ising, dev, sweeps=200_000, discard=20_000, nblocks=2
             "tc_exact": round(2.0 / math.log(1.0 + math.sqrt(2.0)), 6)}
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_msc(w, gpu_value, seconds=2.0):
+    """The multi-spin-coded CPU baseline on the workload's lattice: all-core
+    rate over about `seconds` of sweeps, and the one-core rate of one sweep."""
+    import baselines
+    lat = baselines.Lattice(w.L, seed=w.seed, stream_id=w.stream_id, init=w.init)
+    beta = 1.0 / w.T
+    t0 = time.perf_counter()
+    lat.sweeps(beta, 1, record=True)
+    first = time.perf_counter() - t0
+    n = max(1, min(200, int(seconds / max(first, 1e-6))))
+    t0 = time.perf_counter()
+    lat.sweeps(beta, n, record=True)
+    dt = time.perf_counter() - t0
+    ups = w.L * w.L * n / (dt * 1e9)
+    one = baselines.Lattice(w.L, seed=w.seed, stream_id=w.stream_id, init=w.init, threads=1)
+    t1 = time.perf_counter()
+    one.sweeps(beta, 1, record=True)
+    dt1 = time.perf_counter() - t1
+    ups1 = w.L * w.L / (dt1 * 1e9)
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+    return {"value": ups, "unit": "spin updates/ns", "cores": threads, "kind": "msc-cpu",
+            "value_1core": ups1,
+            "philox": "avx512" if baselines.vector_available() and w.L % 8 == 0 else "scalar",
+            "sample": "%d sweeps of the %dx%d lattice after one untimed (%.1f s); one core: "
+                      "1 sweep (%.1f s)" % (n, w.L, w.L, dt, dt1),
+            "cpu_model": cpu_model(),
+            "gpu_over_cpu": round(gpu_value / ups, 1)}
+
+
 def cpu_baseline(w, sweeps):
     import oracle
     threads = oracle.get_threads()
@@ -376,7 +422,8 @@ def cpu_baseline(w, sweeps):
     ups = w.L * w.L * sweeps / (dt * 1e9)
     return {"value": ups, "unit": "spin updates/ns", "cores": threads, "kind": "oracle",
             "sample": "%d sweeps of the %dx%d lattice (%s start, T=%r), %.1f s"
-                      % (sweeps, w.L, w.L, ["cold +1", "cold -1", "hot"][w.init], w.T, dt)}
+                      % (sweeps, w.L, w.L, ["cold +1", "cold -1", "hot"][w.init], w.T, dt),
+            "cpu_model": cpu_model()}
 
 
 def main():
@@ -507,6 +554,9 @@ def main():
         print("bench: CPU oracle baseline (%d sweeps)" % args.cpu_sweeps, file=sys.stderr,
               flush=True)
         result["cpu_baseline"] = cpu_baseline(w, args.cpu_sweeps)
+    if not args.no_cpu_msc and w.L <= 65536:
+        print("bench: multi-spin-coded CPU baseline", file=sys.stderr, flush=True)
+        result["cpu_msc"] = cpu_msc(w, value)
     print(json.dumps(result), flush=True)
 
 
