@@ -52,6 +52,13 @@ def lib():
         L.oracle_lcg_seed.restype = None
         L.oracle_lcg_sweeps.argtypes = [i64, u32, u32, i64, p8, pu32w, p64]
         L.oracle_lcg_sweeps.restype = None
+        pu64 = ctypes.POINTER(ctypes.c_uint64)
+        L.oracle_pool_fill.argtypes = [u64, u32, u32, u32, i32, pu64, pu64]
+        L.oracle_pool_fill.restype = None
+        L.oracle_pool_address.argtypes = [u64, u32, u32, i32, i32, i32, u64]
+        L.oracle_pool_address.restype = u32
+        L.oracle_pool_sweeps.argtypes = [i64, u32, u32, u64, u32, u32, i64, i32, i32, p8, p64]
+        L.oracle_pool_sweeps.restype = i32
         L.oracle_get_threads.argtypes = []
         L.oracle_get_threads.restype = i32
         L.oracle_set_threads.argtypes = [i32]
@@ -162,6 +169,38 @@ def lcg_sweeps(s: np.ndarray, beta: float, state: np.ndarray, n: int, record: bo
     EM = np.empty((n, 2), dtype=np.int64) if record else None
     lib().oracle_lcg_sweeps(L, t4, t8, n, _p8(s), state.ctypes.data_as(
         ctypes.POINTER(ctypes.c_uint32)), _p64(EM) if record else None)
+    return EM
+
+
+def pool_fill(beta: float, seed: int, stream_id: int, m: int):
+    """Boltzmann-pattern pool of 2^m patterns for beta: (exp4, exp8), each a
+    uint64 array whose bit b of entry p is that bit of pattern p."""
+    t4, t8 = thresholds(beta)
+    e4 = np.empty(1 << m, dtype=np.uint64)
+    e8 = np.empty(1 << m, dtype=np.uint64)
+    pu64 = ctypes.POINTER(ctypes.c_uint64)
+    lib().oracle_pool_fill(seed, stream_id, t4, t8, m, e4.ctypes.data_as(pu64),
+                           e8.ctypes.data_as(pu64))
+    return e4, e8
+
+
+def pool_address(seed: int, stream_id: int, t: int, colour: int, m: int, linear: bool,
+                 j: int) -> int:
+    """Pool pattern read by word j (= y W + w) in sweep t, colour `colour`."""
+    return int(lib().oracle_pool_address(seed, stream_id, t, colour, m, 1 if linear else 0, j))
+
+
+def pool_sweeps(s: np.ndarray, beta: float, seed: int, stream_id: int, t0: int, n: int, m: int,
+                linear: bool, record: bool = True):
+    """n sweeps in place with a pool of 2^m Boltzmann patterns (drawn for
+    beta); linear: one address per 256-word group.  Returns EM[n, 2] or None."""
+    assert s.dtype == np.int8 and s.flags.c_contiguous and s.shape[0] == s.shape[1]
+    t4, t8 = thresholds(beta)
+    EM = np.zeros((n, 2), dtype=np.int64) if record else None
+    rc = lib().oracle_pool_sweeps(s.shape[0], t4, t8, seed, stream_id, t0, n, m,
+                                  1 if linear else 0, _p8(s), _p64(EM) if record else None)
+    if rc != 0:
+        raise ValueError("bad pool size")
     return EM
 
 

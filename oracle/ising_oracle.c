@@ -304,6 +304,128 @@ void oracle_lcg_sweeps(int64_t L, uint32_t t4, uint32_t t8, int64_t n, int8_t *s
     }
 }
 
+/* ================================================================== */
+/* Boltzmann-pattern pools (section 4, and the "unmodified" and        */
+/* "linear" GPU variants of section 5.1 / Table 2): instead of one     */
+/* uniform per site, an update reads two precomputed bit patterns from */
+/* a pool at a random address.  Pattern bit b is, for its own uniform  */
+/* r, exp8 = [r < exp(-8 beta)] and exp4 = [exp(-8 beta) <= r <        */
+/* exp(-4 beta)], and a site with k anti-aligned neighbours flips iff   */
+/* k + 2 exp8 + exp4 >= 2 (Eq. (5)).                                    */
+/* Readings (the paper leaves these to its code):                       */
+/*   - one pattern covers one 64-site word of a colour row: word w of   */
+/*     row y is j = y W + w, W = ceil((L/2) / 64), and site 64 w + b of */
+/*     the row reads bit b;                                             */
+/*   - the pool holds P = 2^m patterns; pattern p's bit b takes the      */
+/*     uniform u of index i = 64 p + b: Philox4x32-10 with the lattice's */
+/*     key and counter (lo32 i/4, hi32 i/4, 2^32 - 1, (stream_id << 2)  */
+/*     | 2), output i mod 4 (a counter no sweep or start uses); exp8 =  */
+/*     [u < t8], exp4 = [t8 <= u < t4] with the integer thresholds of   */
+/*     oracle_threshold; the pool is drawn again when beta changes;     */
+/*   - "random" (each update draws its own address): in sweep t,        */
+/*     colour c, word j reads pattern v >> (32 - m), v = output 0 of     */
+/*     Philox4x32-10 with counter (lo32 j, hi32 j, t, (stream_id << 2)  */
+/*     | c);                                                             */
+/*   - "linear" (one random start per block of threads, which then read */
+/*     consecutive patterns): words are grouped by q = floor(j / 256);  */
+/*     the group draws v as above with counter (lo32 q, hi32 q, t,      */
+/*     (stream_id << 2) | c), and word j reads pattern                  */
+/*     ((v >> (32 - m)) + j mod 256) mod P.                             */
+/* ================================================================== */
+
+/* Pool of 2^m patterns: bit b of e8[p] / e4[p] is exp8 / exp4 of pattern p. */
+void oracle_pool_fill(uint64_t seed, uint32_t stream_id, uint32_t t4, uint32_t t8, int m,
+                      uint64_t *e4, uint64_t *e8)
+{
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    int64_t P = (int64_t)1 << m;
+#pragma omp parallel for schedule(static)
+    for (int64_t p = 0; p < P; ++p) {
+        uint64_t a4 = 0, a8 = 0;
+        for (int b = 0; b < 64; ++b) {
+            uint64_t i = 64 * (uint64_t)p + (uint64_t)b, g = i / 4;
+            uint32_t ctr[4] = {(uint32_t)g, (uint32_t)(g >> 32), 0xFFFFFFFFu,
+                               (stream_id << 2) | 2u};
+            uint32_t out[4];
+            oracle_philox4x32_10(ctr, key, out);
+            uint32_t u = out[i % 4];
+            if (u < t8)
+                a8 |= 1ull << b;
+            else if (u < t4)
+                a4 |= 1ull << b;
+        }
+        e4[p] = a4;
+        e8[p] = a8;
+    }
+}
+
+/* Pool address read by word j in sweep t, colour c (see above). */
+uint32_t oracle_pool_address(uint64_t seed, uint32_t stream_id, uint32_t t, int colour, int m,
+                             int linear, uint64_t j)
+{
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint64_t q = linear ? j / 256 : j;
+    uint32_t ctr[4] = {(uint32_t)q, (uint32_t)(q >> 32), t, (stream_id << 2) | (uint32_t)colour};
+    uint32_t out[4];
+    oracle_philox4x32_10(ctr, key, out);
+    uint32_t a = out[0] >> (32 - m);
+    if (linear)
+        a = (uint32_t)((a + j % 256) & (((uint64_t)1 << m) - 1));
+    return a;
+}
+
+static void pool_colour_step(int64_t L, const uint64_t *e4, const uint64_t *e8, int m,
+                             int linear, uint64_t seed, uint32_t stream_id, uint32_t t,
+                             int colour, int8_t *s)
+{
+    int64_t W = (L / 2 + 63) / 64;
+#pragma omp parallel for schedule(static)
+    for (int64_t y = 0; y < L; ++y) {
+        for (int64_t x = (y + colour) & 1; x < L; x += 2) {
+            int64_t k = x / 2;                          /* colour-local site of the row */
+            uint64_t j = (uint64_t)(y * W + k / 64);
+            uint32_t a = oracle_pool_address(seed, stream_id, t, colour, m, linear, j);
+            int exp8 = (int)((e8[a] >> (k % 64)) & 1u);
+            int exp4 = (int)((e4[a] >> (k % 64)) & 1u);
+            int v = s[y * L + x];
+            int anti = (s[y * L + wrap(x - 1, L)] != v) + (s[y * L + wrap(x + 1, L)] != v) +
+                       (s[wrap(y - 1, L) * L + x] != v) + (s[wrap(y + 1, L) * L + x] != v);
+            if (anti + 2 * exp8 + exp4 >= 2)            /* Eq. (5) */
+                s[y * L + x] = (int8_t)(-v);
+        }
+    }
+}
+
+/* n sweeps from sweep counter t0 with a pool of 2^m patterns drawn for  */
+/* (t4, t8); linear 0: an address per word, 1: per 256-word group.      */
+/* (E, M) into EM after each sweep (may be NULL).  Returns 0, or -1 if  */
+/* m is outside [1, 30] or the pool cannot be allocated.                */
+int oracle_pool_sweeps(int64_t L, uint32_t t4, uint32_t t8, uint64_t seed, uint32_t stream_id,
+                       uint32_t t0, int64_t n, int m, int linear, int8_t *s, int64_t *EM)
+{
+    if (m < 1 || m > 30)
+        return -1;
+    int64_t P = (int64_t)1 << m;
+    uint64_t *e4 = (uint64_t *)malloc((size_t)P * sizeof(uint64_t));
+    uint64_t *e8 = (uint64_t *)malloc((size_t)P * sizeof(uint64_t));
+    if (!e4 || !e8) {
+        free(e4);
+        free(e8);
+        return -1;
+    }
+    oracle_pool_fill(seed, stream_id, t4, t8, m, e4, e8);
+    for (int64_t k = 0; k < n; ++k) {
+        uint32_t t = t0 + (uint32_t)k;
+        pool_colour_step(L, e4, e8, m, linear, seed, stream_id, t, 0, s);
+        pool_colour_step(L, e4, e8, m, linear, seed, stream_id, t, 1, s);
+        if (EM)
+            oracle_measure(L, s, &EM[2 * k], &EM[2 * k + 1]);
+    }
+    free(e4);
+    free(e8);
+    return 0;
+}
+
 /* ------------------------------------------------------------------ */
 /* Light-cone window.  After n sweeps a site depends only on the       */
 /* initial spins and uniforms within Manhattan distance 2n (one site   */
