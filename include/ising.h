@@ -230,12 +230,19 @@ ISING_API ising_status ising_tuning_clear(void);
 /* The paper's own random numbers (alternative dynamics).            */
 /* ---------------------------------------------------------------- */
 
-#define ISING_RNG_PHILOX 0 /* counter-based Philox4x32-10 per site (the default) */
-#define ISING_RNG_LCG 1    /* per-thread linear congruential generators */
+#define ISING_RNG_PHILOX 0      /* counter-based Philox4x32-10 per site (the default) */
+#define ISING_RNG_LCG 1         /* per-thread linear congruential generators */
+#define ISING_RNG_POOL 2        /* Boltzmann-pattern pool, a random address per word */
+#define ISING_RNG_POOL_LINEAR 3 /* Boltzmann-pattern pool read linearly from one random
+                                   start per group of 256 words */
 
 /* Device bytes of the per-thread LCG states of a lattice of side L
  * (2 * L * W uint32, W = ceil((L/2)/64)); 0 for an invalid L. */
 ISING_API size_t ising_lcg_bytes(int64_t L);
+
+/* Device bytes of a Boltzmann-pattern pool of 2^log2_patterns patterns (16
+ * bytes each) for 10 <= log2_patterns <= 28; 0 otherwise. */
+ISING_API size_t ising_pool_bytes(int32_t log2_patterns);
 
 /*
  * Choose the random numbers of the Metropolis decisions (section 5.3).
@@ -250,8 +257,30 @@ ISING_API size_t ising_lcg_bytes(int64_t L);
  * ising_lcg_bytes(L) bytes, 4-byte aligned, kept for the handle's life); the
  * call seeds them asynchronously on the handle's stream.  Needs L % 8 == 0
  * (tiled layout); plain sweeps only (ising_multi_sweep rejects such
- * handles); the hot start is unchanged.  ISING_RNG_PHILOX (dev_state
- * ignored) returns to the default.  EINVAL / ENOMEM on bad arguments.
+ * handles); the hot start is unchanged.
+ *
+ * ISING_RNG_POOL and ISING_RNG_POOL_LINEAR use a pool of Boltzmann patterns
+ * (section 4: bit patterns exp4, exp8 with the flip rule k + 2 exp8 + exp4
+ * >= 2 of Eq. (5); section 5.1 and Table 2 for the two GPU variants).  The
+ * pool holds P = 2^m patterns of 64 sites; bit b of pattern p is drawn from
+ * the uniform u of index i = 64 p + b (Philox4x32-10, the lattice's key,
+ * counter (lo32 i/4, hi32 i/4, 2^32 - 1, stream_id << 2 | 2), output
+ * i mod 4): exp8 = [u < t8], exp4 = [t8 <= u < t4].  In sweep t, colour c,
+ * word j = y W + w of the colour plane reads pattern v >> (32 - m), with v
+ * output 0 of Philox4x32-10 at counter (lo32 j, 0, t, stream_id << 2 | c)
+ * (POOL), or pattern ((v >> (32 - m)) + j mod 256) mod P with v drawn at
+ * counter (lo32 (j / 256), 0, t, stream_id << 2 | c) (POOL_LINEAR: one draw
+ * per group of 256 consecutive words, read linearly).  dev_state is the
+ * pool (caller-owned device memory of exactly ising_pool_bytes(m) bytes,
+ * which fixes m, 16-byte aligned, kept for the handle's life); it is drawn
+ * on the handle's stream now (if beta is set) and again at every
+ * ising_set_beta.  A small pool biases the dynamics (each bit position's
+ * acceptance rate is an empirical fraction over P patterns; the paper
+ * suggests 2^22 to 2^24).  Needs L % 8 == 0 and fewer than 2^32 words per
+ * colour plane; plain sweeps only.
+ *
+ * ISING_RNG_PHILOX (dev_state ignored) returns to the default.  EINVAL /
+ * ENOMEM on bad arguments.
  */
 ISING_API ising_status ising_set_rng(ising_t *h, int32_t kind, void *dev_state,
                                      size_t state_bytes);

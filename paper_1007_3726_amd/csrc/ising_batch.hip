@@ -343,8 +343,9 @@ static ising_status check_batch(ising_t* const* hs, int32_t count, int64_t n, co
   for (int32_t i = 0; i < count; ++i) {
     if (!hs[i]) return fail(ISING_EINVAL, "%s: NULL handle %d", who, i);
     if (!hs[i]->beta_set) return fail(ISING_EINVAL, "%s: handle %d has no beta", who, i);
-    if (hs[i]->lcg)
-      return fail(ISING_EINVAL, "%s: handle %d uses the LCG dynamics (plain sweeps only)", who,
+    if (hs[i]->lcg || hs[i]->pool)
+      return fail(ISING_EINVAL,
+                  "%s: handle %d uses the LCG or pattern-pool dynamics (plain sweeps only)", who,
                   i);
     if (hs[i]->sweep + (uint64_t)n > (1ull << 32))
       return fail(ISING_ERANGE, "%s: counter overflow on handle %d", who, i);

@@ -619,6 +619,155 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
 }
 
 // ---------------------------------------------------------------------
+// Boltzmann-pattern pools (section 4's exp4/exp8 patterns, looked up at a
+// random address per update instead of drawn per site; section 5.1 and
+// Table 2 for the "unmodified" and "linear" GPU variants).  A pattern is a
+// pair of words (r4, r8): bit b of pattern p is [u < t4], [u < t8] for the
+// uniform u of index i = 64 p + b, Philox4x32-10 with the lattice's key and
+// counter (lo32 i/4, hi32 i/4, 2^32 - 1, stream_id << 2 | 2).  The paper's
+// encoding is exp8 = r8, exp4 = r4 & ~r8, and its flip rule k + 2 exp8 +
+// exp4 >= 2 is flip_mask's.  In sweep t, colour c, word j = y W + w draws
+// v = output 0 of Philox4x32-10 with counter (lo32 q, hi32 q, t,
+// stream_id << 2 | c), q = j (random addresses) or q = j / 256 (linear
+// reads), and reads pattern v >> (32 - m), plus j mod 256 for linear reads
+// (mod 2^m).
+// ---------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_pool_fill(uint64_t* pool, int64_t P, uint32_t k0,
+                                                   uint32_t k1, uint32_t sid4, uint32_t t4,
+                                                   uint32_t t8) {
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < P;
+       p += (int64_t)gridDim.x * blockDim.x) {
+    uint64_t r4, r8;
+    masks_shift<true>(16u * (uint32_t)p, 0u, 16, k0, k1, 0xFFFFFFFFu, sid4 | 2u, t4, t8, r4,
+                      r8);
+    pool[2 * p] = r4;
+    pool[2 * p + 1] = r8;
+  }
+}
+
+hipError_t launch_pool_fill(hipStream_t st, uint64_t* pool, int m, uint32_t k0, uint32_t k1,
+                            uint32_t sid4, uint32_t t4, uint32_t t8) {
+  const int64_t P = (int64_t)1 << m;
+  const int64_t blocks = std::min<int64_t>((P + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_pool_fill, dim3((unsigned)blocks), dim3(256), 0, st, pool, P, k0, k1,
+                     sid4, t4, t8);
+  return hipGetLastError();
+}
+
+// One tile of a pool colour step: 4 waves x 4 words per lane on the flat
+// mapping (wave task k = words 256 k .. 256 k + 255, which is one linear
+// group).  Every lane first draws the addresses of its 4 words and issues
+// all their loads (own word, 4 neighbours, pattern), then updates them: the
+// work per word is small, so the loads of the 4 words overlap.
+template <int C, bool EM, bool FULL, bool LINEAR>
+__device__ __forceinline__ void pool_tile(const TileArgs& a, int64_t tidx, uint32_t& anti,
+                                          uint32_t& up) {
+  constexpr int RPW = 4;
+  const Geom& g = a.g;
+  uint64_t* __restrict__ self = a.planes + (C ? a.plane_words : 0);
+  const uint64_t* __restrict__ other = a.planes + (C ? 0 : a.plane_words);
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t W = g.W;
+  const uint32_t ctr3 = a.sid4 | (uint32_t)C;
+  const int64_t task = tidx * 4 + wave;
+  const ulonglong2* __restrict__ pool = (const ulonglong2*)a.pool;
+  uint32_t lin = 0;
+  if (LINEAR) {  // one draw per wave task (= 256-word group)
+    uint32_t x0 = (uint32_t)task, x1 = 0, x2 = a.t, x3 = ctr3;
+    philox4x32_10(x0, x1, x2, x3, a.k0, a.k1);
+    lin = x0 >> a.pool_shift;
+  }
+  uint32_t iw[RPW];
+  int32_t yv[RPW], wv[RPW];
+  bool ok[RPW];
+  uint64_t s[RPW], n0[RPW], n2[RPW], n3[RPW], sd[RPW];
+  ulonglong2 pat[RPW];
+#pragma unroll
+  for (int j = 0; j < RPW; ++j) {
+    const int64_t i = (task * RPW + j) * 64 + (threadIdx.x & 63);
+    ok[j] = i < a.plane_words;
+    const uint32_t iu = ok[j] ? (uint32_t)i : 0u;  // plane_words < 2^32 for pool lattices
+    uint32_t y, w;
+    if (W == 1) {
+      y = iu;
+      w = 0;
+    } else {
+      uint32_t q = (uint32_t)(((uint64_t)iu * a.wdiv_m) >> 32);
+      int64_t r = (int64_t)iu - (int64_t)q * W;
+      if (r < 0) {
+        q -= 1u;
+        r += W;
+      }
+      y = q;
+      w = (uint32_t)r;
+    }
+    iw[j] = iu;
+    yv[j] = (int32_t)y;
+    wv[j] = (int32_t)w;
+    uint32_t addr;
+    if (LINEAR) {
+      addr = (lin + (iu & 255u)) & a.pool_mask;
+    } else {
+      uint32_t x0 = iu, x1 = 0, x2 = a.t, x3 = ctr3;
+      philox4x32_10(x0, x1, x2, x3, a.k0, a.k1);
+      addr = x0 >> a.pool_shift;
+    }
+    const int64_t ym = y == 0 ? g.L - 1 : (int64_t)y - 1;
+    const int64_t yp = (int64_t)y == g.L - 1 ? 0 : (int64_t)y + 1;
+    const bool left = ((y + (uint32_t)C) & 1u) == 0;
+    const int64_t ws = left ? (w > 0 ? w - 1 : W - 1) : ((int64_t)w < W - 1 ? w + 1 : 0);
+    s[j] = self[iu];
+    n0[j] = other[iu];
+    n2[j] = other[ym * W + w];
+    n3[j] = other[yp * W + w];
+    sd[j] = other[(int64_t)y * W + ws];
+    pat[j] = pool[addr];
+  }
+#pragma unroll
+  for (int j = 0; j < RPW; ++j) {
+    if (!ok[j]) continue;
+    const int32_t y = yv[j], w = wv[j];
+    const bool left = ((y + C) & 1) == 0;
+    Nbr n;
+    n.n0 = n0[j];
+    n.n2 = n2[j];
+    n.n3 = n3[j];
+    if (FULL) {
+      n.n1 = left ? ((n0[j] << 1) | (sd[j] >> 63)) : ((n0[j] >> 1) | (sd[j] << 63));
+    } else {
+      const uint64_t bl = w > 0 ? (sd[j] >> 63) : ((sd[j] >> (g.nb_last - 1)) & 1ull);
+      const uint64_t br = w < W - 1 ? (sd[j] << 63) : ((sd[j] & 1ull) << (g.nb_last - 1));
+      n.n1 = left ? ((n0[j] << 1) | bl) : ((n0[j] >> 1) | br);
+    }
+    const uint64_t valid = (FULL || w < W - 1) ? ~0ull : low_mask(g.nb_last);
+    const uint64_t s_new = s[j] ^ (flip_mask(s[j], n, pat[j].x, pat[j].y) & valid);
+    __hip_atomic_store(&self[iw[j]], s_new, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (C == 1 && EM) count_word(s_new, n, valid, anti, up);
+  }
+}
+
+template <int C, bool EM, bool FULL, bool LINEAR>
+__global__ __launch_bounds__(256) void k_pool_sweep(TileArgs a) {
+  __shared__ uint64_t red64[8];
+  __shared__ uint64_t red[8];
+  if (C == 0 && a.prev_EM != nullptr && blockIdx.x == 0)
+    finalize_partials(a.prev_part, a.prev_blocks, a.g.L, a.prev_EM, red64);
+  const int G = gridDim.x;
+  const int b = blockIdx.x;
+  const int lb = (G % 8 == 0) ? (b % 8) * (G / 8) + b / 8 : b;
+  uint32_t anti = 0, up = 0;
+  for (int64_t tidx = lb; tidx < a.tiles; tidx += G) pool_tile<C, EM, FULL, LINEAR>(a, tidx, anti, up);
+  if (C == 1 && EM) {
+    uint64_t sa, sp;
+    block_sum2(anti, up, red, sa, sp);
+    if (threadIdx.x == 0) {
+      a.part[2 * blockIdx.x] = sa;
+      a.part[2 * blockIdx.x + 1] = sp;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------
 // Strip form of the wide half-sweep: one wave owns 64 consecutive words of
 // RPW consecutive rows (a "task") and walks down them, keeping the other
 // colour's rows y-1, y, y+1 in registers and loading row y+2, the
@@ -985,6 +1134,33 @@ void make_flat(TileArgs& a, bool always) {
   a.wdiv_m = W == 1 ? 0u : (uint32_t)((1ull << 32) / (uint64_t)W + 1ull);
   const int64_t per_tile = 256 * (int64_t)a.RPW;
   a.tiles = (words + per_tile - 1) / per_tile;
+}
+
+template <bool LINEAR>
+static void launch_pool_sweep_v(hipStream_t st, int colour, const TileArgs& a, int blocks) {
+  const bool em = (colour == 1) ? (a.part != nullptr) : false;
+  const bool full = a.g.nb_last == 64;
+#define ISING_POOL(C, E, F) \
+  hipLaunchKernelGGL((k_pool_sweep<C, E, F, LINEAR>), dim3(blocks), dim3(256), 0, st, a)
+  if (colour == 0) {
+    if (full) ISING_POOL(0, false, true);
+    else ISING_POOL(0, false, false);
+  } else if (em) {
+    if (full) ISING_POOL(1, true, true);
+    else ISING_POOL(1, true, false);
+  } else {
+    if (full) ISING_POOL(1, false, true);
+    else ISING_POOL(1, false, false);
+  }
+#undef ISING_POOL
+}
+
+hipError_t launch_pool_sweep(hipStream_t st, int colour, const TileArgs& a, int blocks) {
+  if (a.pool_linear)
+    launch_pool_sweep_v<true>(st, colour, a, blocks);
+  else
+    launch_pool_sweep_v<false>(st, colour, a, blocks);
+  return hipGetLastError();
 }
 
 hipError_t launch_strip_sweep(hipStream_t st, int colour, const TileArgs& a, int blocks) {

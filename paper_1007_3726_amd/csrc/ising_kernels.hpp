@@ -67,6 +67,13 @@ struct TileArgs {
   // q W > i.
   int32_t flat;
   uint32_t wdiv_m;
+  // Boltzmann-pattern-pool dynamics (plain tiles, flat mapping, RPW = 4):
+  // 2^m patterns of (r4, r8) word pairs, or null; a word reads pattern
+  // v >> pool_shift (pool_shift = 32 - m) of its own Philox draw, or, with
+  // pool_linear, of its 256-word group's draw plus its offset in the group
+  const uint64_t* pool;
+  uint32_t pool_shift, pool_mask;
+  int32_t pool_linear;
 };
 
 // Switch tile arguments of a lattice to the flat mapping (see
@@ -83,6 +90,11 @@ hipError_t launch_finalize_em(hipStream_t st, const uint64_t* part, int blocks, 
                               int64_t* EM);
 // Thread seeds of the LCG dynamics: state[j] = s0 * 16807^j mod 2^32.
 hipError_t launch_lcg_seed(hipStream_t st, uint32_t* state, int64_t n, uint32_t s0);
+// Pattern pool: 2^m (r4, r8) pairs drawn for thresholds (t4, t8).
+hipError_t launch_pool_fill(hipStream_t st, uint64_t* pool, int m, uint32_t k0, uint32_t k1,
+                            uint32_t sid4, uint32_t t4, uint32_t t8);
+// Colour step of the pool dynamics (TileArgs with flat = 1, RPW = 4, pool set).
+hipError_t launch_pool_sweep(hipStream_t st, int colour, const TileArgs& a, int blocks);
 
 // Batched sweeps (see ising_kernels.hip).
 struct FusedLattice {

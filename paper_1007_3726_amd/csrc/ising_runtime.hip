@@ -99,7 +99,7 @@ SweepArgs sweep_args(const ising_lattice* h, uint32_t t, int64_t* EM) {
 }
 
 bool strip_form(const ising_lattice* h) {
-  return h->tune.form == 1 && h->g.W >= kWideMinWords && h->lcg == nullptr;
+  return h->tune.form == 1 && h->g.W >= kWideMinWords && h->lcg == nullptr && h->pool == nullptr;
 }
 
 // Shape of the tiled half-sweep for this lattice; false when it does not
@@ -172,7 +172,7 @@ bool strip_args(const ising_lattice* h, TileArgs* out) {
 }
 
 bool use_small_path(const ising_lattice* h) {
-  return h->lcg == nullptr &&
+  return h->lcg == nullptr && h->pool == nullptr &&
          2 * h->plane_words * (int64_t)sizeof(uint64_t) <= h->tune.small_lds_bytes;
 }
 
@@ -180,6 +180,52 @@ bool use_small_path(const ising_lattice* h) {
 static void lcg_decision(uint32_t t, uint32_t* d, uint32_t* m) {
   *d = t ? t - 1u : 0u;
   *m = t ? (uint32_t)(2ull * t - 1ull) : 0u;
+}
+
+// Tile arguments of the pool dynamics: flat mapping with 4 words per lane.
+static bool pool_tile_args(const ising_lattice* h, TileArgs* out) {
+  TileArgs ta;
+  if (!tile_args(h, &ta) || h->plane_words >= (1ll << 32)) return false;
+  ta.RPW = 4;
+  make_flat(ta, true);
+  *out = ta;
+  return true;
+}
+
+static ising_status enqueue_pool_sweeps(ising_lattice* h, int64_t n, int64_t* dev_EM) {
+  TileArgs ta;
+  if (!pool_tile_args(h, &ta))
+    return fail(ISING_EINVAL, "pattern-pool dynamics need L %% 8 == 0 and < 2^32 words per plane");
+  ta.pool = h->pool;
+  ta.pool_shift = (uint32_t)(32 - h->pool_m);
+  ta.pool_mask = (uint32_t)((1ull << h->pool_m) - 1);
+  ta.pool_linear = h->pool_linear ? 1 : 0;
+  const int blocks = (int)std::min<int64_t>(ta.tiles, kMaxSweepBlocks);
+  for (int64_t k = 0; k < n; ++k) {
+    ta.t = (uint32_t)(h->sweep + (uint64_t)k);
+    ta.prev_EM = (dev_EM && k > 0) ? dev_EM + 2 * (k - 1) : nullptr;
+    ta.prev_part = h->part[(k + 1) & 1];
+    ta.prev_blocks = blocks;
+    ta.part = nullptr;
+    hipError_t e = launch_pool_sweep(h->stream, 0, ta, blocks);
+    if (e != hipSuccess) return hip_fail(e, "colour-0 pool half-sweep launch");
+    ta.prev_EM = nullptr;
+    ta.part = dev_EM ? h->part[k & 1] : nullptr;
+    e = launch_pool_sweep(h->stream, 1, ta, blocks);
+    if (e != hipSuccess) return hip_fail(e, "colour-1 pool half-sweep launch");
+  }
+  if (dev_EM) {
+    hipError_t e = launch_finalize_em(h->stream, h->part[(n - 1) & 1], blocks, h->L,
+                                      dev_EM + 2 * (n - 1));
+    if (e != hipSuccess) return hip_fail(e, "E/M finalisation launch");
+  }
+  return ISING_OK;
+}
+
+static ising_status fill_pool(ising_lattice* h) {
+  hipError_t e = launch_pool_fill(h->stream, h->pool, h->pool_m, (uint32_t)h->seed,
+                                  (uint32_t)(h->seed >> 32), h->stream_id << 2, h->t4, h->t8);
+  return e == hipSuccess ? ISING_OK : hip_fail(e, "pattern pool fill");
 }
 
 ising_status enqueue_sweeps(ising_lattice* h, int64_t n, int64_t* dev_EM) {
@@ -203,6 +249,7 @@ ising_status enqueue_sweeps(ising_lattice* h, int64_t n, int64_t* dev_EM) {
     return ISING_OK;
   }
   TileArgs ta;
+  if (h->pool) return enqueue_pool_sweeps(h, n, dev_EM);
   const bool strip = strip_args(h, &ta);
   if (strip || tile_args(h, &ta)) {
     if (!strip) make_flat(ta);  // direct-load tiles: every lane busy at any W
@@ -341,7 +388,13 @@ ising_status ising_set_beta(ising_t* h, double beta) {
   h->l4 = lcg_threshold(beta, 4);
   h->l8 = lcg_threshold(beta, 8);
   h->beta_set = true;
+  if (h->pool) return fill_pool(h);  // the patterns encode this temperature
   return ISING_OK;
+}
+
+size_t ising_pool_bytes(int32_t log2_patterns) {
+  if (log2_patterns < 10 || log2_patterns > 28) return 0;
+  return (size_t)16 << log2_patterns;
 }
 
 size_t ising_lcg_bytes(int64_t L) {
@@ -354,7 +407,26 @@ ising_status ising_set_rng(ising_t* h, int32_t kind, void* dev_state, size_t sta
   if (!h) return fail(ISING_EINVAL, "ising_set_rng: NULL handle");
   if (kind == ISING_RNG_PHILOX) {
     h->lcg = nullptr;
+    h->pool = nullptr;
     return ISING_OK;
+  }
+  if (kind == ISING_RNG_POOL || kind == ISING_RNG_POOL_LINEAR) {
+    TileArgs pa;
+    if (!pool_tile_args(h, &pa))
+      return fail(ISING_EINVAL,
+                  "ising_set_rng: pattern pools need L %% 8 == 0 and < 2^32 words per plane");
+    int m = 10;
+    while (m <= 28 && ising_pool_bytes(m) != state_bytes) ++m;
+    if (m > 28)
+      return fail(ISING_EINVAL, "ising_set_rng: pool bytes must be ising_pool_bytes(m), 10 <= m <= 28");
+    if (!dev_state) return fail(ISING_EINVAL, "ising_set_rng: NULL pool buffer");
+    if (((uintptr_t)dev_state & 15u) != 0)
+      return fail(ISING_EINVAL, "ising_set_rng: pool buffer must be 16-byte aligned");
+    h->lcg = nullptr;
+    h->pool = (uint64_t*)dev_state;
+    h->pool_m = m;
+    h->pool_linear = kind == ISING_RNG_POOL_LINEAR;
+    return h->beta_set ? fill_pool(h) : ISING_OK;
   }
   if (kind != ISING_RNG_LCG) return fail(ISING_EINVAL, "ising_set_rng: unknown kind %d", kind);
   TileArgs ta;
@@ -369,6 +441,7 @@ ising_status ising_set_rng(ising_t* h, int32_t kind, void* dev_state, size_t sta
                                  (uint32_t)h->seed);
   if (e != hipSuccess) return hip_fail(e, "ising_set_rng: seeding");
   h->lcg = (uint32_t*)dev_state;
+  h->pool = nullptr;
   return ISING_OK;
 }
 

@@ -56,6 +56,9 @@ struct ising_lattice {
   uint32_t l4, l8;      // LCG thresholds min(floor(exp(-beta dE) 2^31), 2^31)
   bool beta_set;
   uint32_t* lcg;        // device: per-thread LCG states [2][L][W] (caller's), or null
+  uint64_t* pool;       // device: Boltzmann-pattern pool, 2^pool_m (r4, r8) pairs (caller's), or null
+  int32_t pool_m;
+  bool pool_linear;     // pool read linearly from one draw per 256-word group
   uint64_t sweep;       // counter of the next sweep
   hipStream_t stream;
   int device;

@@ -24,6 +24,8 @@ ISING_FORM_TILE = 0
 ISING_FORM_STRIP = 1
 ISING_RNG_PHILOX = 0
 ISING_RNG_LCG = 1
+ISING_RNG_POOL = 2
+ISING_RNG_POOL_LINEAR = 3
 
 INIT_COLD_UP = 0
 INIT_COLD_DOWN = 1
@@ -110,6 +112,7 @@ def lib():
         "ising_server_stats": ([vp, P(i64)], i32),
         "ising_server_destroy": ([vp], i32),
         "ising_lcg_bytes": ([i64], ctypes.c_size_t),
+        "ising_pool_bytes": ([i32], ctypes.c_size_t),
         "ising_set_rng": ([vp, i32, vp, ctypes.c_size_t], i32),
         "ising_reweight": ([i32, P(vp), P(i64), P(i64), P(ctypes.c_double), i32, P(i32),
                             P(ctypes.c_double), i32, vp, vp, vp], i32),
@@ -159,6 +162,10 @@ def ising_lcg_bytes(L: int) -> int:
     return int(lib().ising_lcg_bytes(L))
 
 
+def ising_pool_bytes(log2_patterns: int) -> int:
+    return int(lib().ising_pool_bytes(log2_patterns))
+
+
 def ising_version() -> str:
     return lib().ising_version().decode()
 
@@ -204,9 +211,20 @@ class Lattice:
         self.lcg_buf = _dev_alloc(max(nbytes, 4), self.device)
         check(lib().ising_set_rng(self.h, ISING_RNG_LCG, self.lcg_buf.data_ptr(), nbytes))
 
+    def use_pool(self, log2_patterns: int = 22, linear: bool = False):
+        """Switch to the Boltzmann-pattern-pool dynamics (ising_set_rng): a
+        pool of 2^log2_patterns patterns, allocated here and drawn on the
+        lattice's stream; linear reads one random start per 256 words."""
+        nbytes = ising_pool_bytes(log2_patterns)
+        self.pool_buf = _dev_alloc(max(nbytes, 16), self.device)
+        kind = ISING_RNG_POOL_LINEAR if linear else ISING_RNG_POOL
+        check(lib().ising_set_rng(self.h, kind, self.pool_buf.data_ptr(), nbytes))
+        self.lcg_buf = None
+
     def use_philox(self):
         check(lib().ising_set_rng(self.h, ISING_RNG_PHILOX, None, 0))
         self.lcg_buf = None
+        self.pool_buf = None
 
     def lcg_states(self):
         """Host copy of the LCG states as uint32 (2, L, W)."""

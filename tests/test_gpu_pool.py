@@ -1,0 +1,110 @@
+"""The Boltzmann-pattern-pool dynamics (section 4's exp4/exp8 pool, the
+"unmodified" and "linear" GPU variants of Table 2) on the GPU against the
+oracle's pool mode: bit-exact spins and per-sweep int64 (E, M) on ragged
+lattices (partial last words, one-word rows, W = 3 and 65), at several
+temperatures including beta = 0 and +inf, pool sizes 2^10 .. 2^16, the
+pool drawn again when beta changes, lattices past one 256-word group per
+row block; argument checks."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def I():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1007_3726_amd import ising
+    ising.lib()
+    return ising
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.mark.parametrize("linear", [False, True])
+@pytest.mark.parametrize("L", [8, 16, 24, 64, 136, 200, 264])
+@pytest.mark.parametrize("beta", [1 / 2.269185, 0.0, math.inf, 1 / 1.5])
+def test_every_sweep_bit_exact(I, L, beta, linear):
+    n, m, seed, sid = 6, 10, 7, 3
+    _say("case L=%d beta=%r linear=%s" % (L, beta, linear))
+    lat = I.Lattice(L, seed=seed, stream_id=sid, init=workloads.INIT_HOT, beta=beta)
+    lat.use_pool(m, linear)
+    s = oracle.init(L, seed, sid, workloads.INIT_HOT)
+    for t in range(n):
+        em = lat.sweep_em(1).cpu().numpy()
+        oem = oracle.pool_sweeps(s, beta, seed, sid, t, 1, m, linear)
+        assert np.array_equal(em, oem), t
+        assert np.array_equal(lat.get_spins(), s), t
+
+
+@pytest.mark.parametrize("L,m,linear", [(1024, 16, True), (1024, 12, False), (2056, 14, True),
+                                        (8320, 16, False), (8320, 16, True)])
+def test_larger_lattices(I, L, m, linear):
+    n, beta = 3, 1 / 2.3
+    _say("case L=%d m=%d linear=%s" % (L, m, linear))
+    lat = I.Lattice(L, seed=5, init=workloads.INIT_HOT, beta=beta)
+    lat.use_pool(m, linear)
+    em = lat.sweep_em(n).cpu().numpy()
+    s = oracle.init(L, 5, 0, workloads.INIT_HOT)
+    oem = oracle.pool_sweeps(s, beta, 5, 0, 0, n, m, linear)
+    assert np.array_equal(em, oem)
+    assert np.array_equal(lat.get_spins(), s)
+
+
+@pytest.mark.parametrize("linear", [False, True])
+def test_pool_is_drawn_again_when_beta_changes(I, linear):
+    L, m = 136, 12
+    lat = I.Lattice(L, seed=2, init=workloads.INIT_HOT, beta=0.3)
+    lat.use_pool(m, linear)
+    s = oracle.init(L, 2, 0, workloads.INIT_HOT)
+    e1 = lat.sweep_em(3).cpu().numpy()
+    o1 = oracle.pool_sweeps(s, 0.3, 2, 0, 0, 3, m, linear)
+    lat.set_beta(0.6)
+    e2 = lat.sweep_em(3).cpu().numpy()
+    o2 = oracle.pool_sweeps(s, 0.6, 2, 0, 3, 3, m, linear)
+    assert np.array_equal(e1, o1) and np.array_equal(e2, o2)
+    assert np.array_equal(lat.get_spins(), s)
+
+
+def test_switching_dynamics(I):
+    L, beta = 64, 0.4
+    a = I.Lattice(L, seed=2, init=workloads.INIT_HOT, beta=beta)
+    ref = a.sweep_em(4).cpu().numpy()
+    b = I.Lattice(L, seed=2, init=workloads.INIT_HOT, beta=beta)
+    b.use_pool(10)
+    b.use_lcg()
+    b.use_pool(10, True)
+    b.use_philox()
+    assert np.array_equal(b.sweep_em(4).cpu().numpy(), ref)
+
+
+def test_argument_checks(I):
+    import torch
+    assert I.ising_pool_bytes(10) == 16 << 10 and I.ising_pool_bytes(9) == 0
+    assert I.ising_pool_bytes(28) == 16 << 28 and I.ising_pool_bytes(29) == 0
+    lat = I.Lattice(66, init=workloads.INIT_HOT, beta=0.4)  # L % 8 != 0
+    buf = torch.empty(I.ising_pool_bytes(10), dtype=torch.uint8, device="cuda")
+    with pytest.raises(I.IsingError):
+        I.check(I.lib().ising_set_rng(lat.h, I.ISING_RNG_POOL, buf.data_ptr(), buf.numel()))
+    lat2 = I.Lattice(64, init=workloads.INIT_HOT, beta=0.4)
+    with pytest.raises(I.IsingError):  # not 16 * 2^m bytes
+        I.check(I.lib().ising_set_rng(lat2.h, I.ISING_RNG_POOL, buf.data_ptr(), 3 << 12))
+    with pytest.raises(I.IsingError):  # misaligned
+        I.check(I.lib().ising_set_rng(lat2.h, I.ISING_RNG_POOL, buf.data_ptr() + 8, 16 << 10))
+    with pytest.raises(I.IsingError):
+        I.check(I.lib().ising_set_rng(lat2.h, I.ISING_RNG_POOL_LINEAR, None, 16 << 10))
+    lat2.use_pool(10)
+    EM = torch.empty((2, 2), dtype=torch.int64, device="cuda")
+    with pytest.raises(I.IsingError):
+        I.multi_sweep([lat2], 2, [EM])  # batched path: Philox only
