@@ -10,6 +10,9 @@ Also reported on the same JSON line:
   roofline      - the half-sweep kernel against the integer VALU issue peak;
   cpu_baseline  - the CPU oracle timed on a bounded sample of the same
                   workload on this host's cores (a baseline, not the target);
+  lcg, pool     - the plain workload with the paper's own random numbers:
+                  per-thread LCGs, and Boltzmann-pattern pools read at random
+                  addresses or linearly;
   cpu_msc       - the multi-spin-coded CPU baseline (same chain, 64 spins per
                   word, vectorised Philox) on the same workload, all cores and
                   one core: the kind of CPU program the paper's speed-ups are
@@ -63,6 +66,8 @@ def parse():
                    help="skip the multi-spin-coded CPU baseline")
     p.add_argument("--no-lcg", action="store_true",
                    help="skip the plain workload with the paper's LCG random numbers")
+    p.add_argument("--no-pool", action="store_true",
+                   help="skip the plain workload with Boltzmann-pattern pools")
     p.add_argument("--no-autotune", action="store_true",
                    help="skip the autotuner report (profiling runs: no trial launches)")
     p.add_argument("--served-requests", type=int, default=200,
@@ -338,6 +343,48 @@ def bench_lcg(torch, ising, dev, w, steps):
             "roofline_frac": round(achieved / VALU_PEAK_LANE_OPS, 4)}
 
 
+# Algorithmic HBM bytes per update of the pattern-pool dynamics: the two
+# colour planes (3 bits: read both colours once, write one) plus one
+# 16-byte (r4, r8) pattern pair per 64-site word.
+POOL_BYTES_PER_UPDATE = 3 / 8 + 16 / 64
+HBM_PEAK_BYTES = 8.0e12
+
+
+def bench_pool(torch, ising, dev, w, steps, log2_patterns=22):
+    """The plain workload with section 4's Boltzmann-pattern pool instead of
+    per-site uniforms: a random pool address per word (Table 2's
+    "unmodified" GPU variant) and linear reads from one random start per
+    256 words (its "linear" variant)."""
+    out = {"log2_patterns": log2_patterns,
+           "pool_bytes": ising.ising_pool_bytes(log2_patterns),
+           "bytes_per_update": POOL_BYTES_PER_UPDATE}
+    N = w.L * w.L
+    for name, linear in (("random", False), ("linear", True)):
+        lat = ising.Lattice(w.L, seed=w.seed, stream_id=w.stream_id, init=w.init,
+                            beta=1.0 / w.T, device=dev)
+        lat.use_pool(log2_patterns, linear)
+        EM = torch.empty((w.sweeps, 2), dtype=torch.int64, device=dev)
+        stream = lat.stream
+        lat.sweep(w.sweeps, EM)
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(steps):
+            lat.sweep(w.sweeps, EM)
+        b.record(stream)
+        b.synchronize()
+        ms = a.elapsed_time(b)
+        assert tuple(EM[-1].cpu().tolist()) == lat.measure(), "E/M disagrees with a recount"
+        ups = N * w.sweeps * steps / (ms * 1e6)
+        out[name] = {"value": round(ups, 2), "unit": "spin updates/ns",
+                     "avg_launch_us": round(ms * 1e3 / (2 * w.sweeps * steps), 3),
+                     "hbm_frac": round(ups * 1e9 * POOL_BYTES_PER_UPDATE / HBM_PEAK_BYTES, 4)}
+        del lat, EM
+        torch.cuda.empty_cache()
+    return out
+
+
 def bench_fss_proof(torch, ising, dev, sweeps=200_000, discard=20_000, nblocks=20):
     """The paper's proof of concept (section 2): Binder cumulants of small
     lattices (L = 8..64, six temperatures in [2.15, 2.40], long runs on the
@@ -525,6 +572,9 @@ def main():
         print("bench: plain workload with the paper's LCG random numbers", file=sys.stderr,
               flush=True)
         result["lcg"] = bench_lcg(torch, ising, dev, w, args.steps)
+    if not args.no_pool:
+        print("bench: plain workload with Boltzmann-pattern pools", file=sys.stderr, flush=True)
+        result["pool"] = bench_pool(torch, ising, dev, w, args.steps)
     if args.copy_calibration:
         # a plain copy of known size: 1 GiB read + 1 GiB written
         src = torch.ones(1 << 30, dtype=torch.uint8, device=dev)
