@@ -102,12 +102,45 @@ __device__ __forceinline__ Nbr gather(Ptr o, const Geom& g, int c, int64_t y, in
 // a_i = s ^ n_i marks anti-aligned neighbours; with k = sum a_i the site
 // flips iff k + [u < t4] + [u < t8] >= 2.  Since t8 <= t4, [u < t8] implies
 // [u < t4], so flip = (k >= 2) | ((k >= 1) & r4) | r8.
+// Truth-table immediate of a three-input bit function for v_bitop3: bit
+// 4 a + 2 b + c of the table is f(a, b, c) (a, b, c the first, second and
+// third operand).
+template <typename F>
+constexpr uint32_t bitop3_table(F f) {
+  uint32_t t = 0;
+  for (int i = 0; i < 8; ++i) t |= (uint32_t)(f((i >> 2) & 1, (i >> 1) & 1, i & 1) & 1) << i;
+  return t;
+}
+
+__device__ __forceinline__ uint32_t flip_half(uint32_t s, uint32_t n0, uint32_t n1, uint32_t n2,
+                                              uint32_t n3, uint32_t r4, uint32_t r8) {
+  // both neighbours of a pair anti-aligned / at least one of them
+  constexpr uint32_t kBoth = bitop3_table([](int a, int b, int c) { return (a ^ b) & (a ^ c); });
+  constexpr uint32_t kEither = bitop3_table([](int a, int b, int c) { return (a ^ b) | (a ^ c); });
+  constexpr uint32_t kOrAnd = bitop3_table([](int a, int b, int c) { return a | (b & c); });
+  constexpr uint32_t kOrThenAnd = bitop3_table([](int a, int b, int c) { return (a | b) & c; });
+  constexpr uint32_t kOr3 = bitop3_table([](int a, int b, int c) { return a | b | c; });
+  const uint32_t p01 = __builtin_amdgcn_bitop3_b32(s, n0, n1, kBoth);
+  const uint32_t p23 = __builtin_amdgcn_bitop3_b32(s, n2, n3, kBoth);
+  const uint32_t o01 = __builtin_amdgcn_bitop3_b32(s, n0, n1, kEither);
+  const uint32_t o23 = __builtin_amdgcn_bitop3_b32(s, n2, n3, kEither);
+  // one anti-aligned neighbour in each pair: (a0 ^ a1) & (a2 ^ a3), where
+  // a0 ^ a1 = n0 ^ n1 (s cancels)
+  const uint32_t ge2 = __builtin_amdgcn_bitop3_b32(p01, n0 ^ n1, n2 ^ n3, kOrAnd);
+  const uint32_t one = __builtin_amdgcn_bitop3_b32(o01, o23, r4, kOrThenAnd);
+  return __builtin_amdgcn_bitop3_b32(ge2, p23, one, kOr3) | r8;
+}
+
 __device__ __forceinline__ uint64_t flip_mask(uint64_t s, const Nbr& n, uint64_t r4, uint64_t r8) {
-  const uint64_t a0 = s ^ n.n0, a1 = s ^ n.n1, a2 = s ^ n.n2, a3 = s ^ n.n3;
-  const uint64_t x01 = a0 ^ a1, x23 = a2 ^ a3;
-  const uint64_t ge2 = (a0 & a1) | (a2 & a3) | (x01 & x23);
-  const uint64_t any = a0 | a1 | a2 | a3;
-  return ge2 | (any & r4) | r8;
+  // k >= 2, or k >= 1 with r4, or r8 (r8 implies r4): the flip rule of
+  // Eq. (5), evaluated per 32-bit half with three-input bit operations
+  const uint32_t lo = flip_half((uint32_t)s, (uint32_t)n.n0, (uint32_t)n.n1, (uint32_t)n.n2,
+                                (uint32_t)n.n3, (uint32_t)r4, (uint32_t)r8);
+  const uint32_t hi = flip_half((uint32_t)(s >> 32), (uint32_t)(n.n0 >> 32),
+                                (uint32_t)(n.n1 >> 32), (uint32_t)(n.n2 >> 32),
+                                (uint32_t)(n.n3 >> 32), (uint32_t)(r4 >> 32),
+                                (uint32_t)(r8 >> 32));
+  return ((uint64_t)hi << 32) | lo;
 }
 
 // Insert the comparison results of one Philox block (4 consecutive sites,
