@@ -13,6 +13,8 @@ Also reported on the same JSON line:
   lcg, pool     - the plain workload with the paper's own random numbers:
                   per-thread LCGs, and Boltzmann-pattern pools read at random
                   addresses or linearly;
+  table2        - the paper's benchmark point (4096^2 at 0.99 T_C) with every
+                  update variant, batched, and the multi-spin CPU baseline;
   cpu_msc       - the multi-spin-coded CPU baseline (same chain, 64 spins per
                   word, vectorised Philox) on the same workload, all cores and
                   one core: the kind of CPU program the paper's speed-ups are
@@ -66,6 +68,8 @@ def parse():
                    help="skip the multi-spin-coded CPU baseline")
     p.add_argument("--no-lcg", action="store_true",
                    help="skip the plain workload with the paper's LCG random numbers")
+    p.add_argument("--no-table2", action="store_true",
+                   help="skip the paper's 4096^2 benchmark point with every variant")
     p.add_argument("--no-pool", action="store_true",
                    help="skip the plain workload with Boltzmann-pattern pools")
     p.add_argument("--no-autotune", action="store_true",
@@ -385,6 +389,61 @@ def bench_pool(torch, ising, dev, w, steps, log2_patterns=22):
     return out
 
 
+def bench_table2(torch, ising, dev, reps=3):
+    """The paper's benchmark point (Table 2: one 4096^2 lattice at
+    T = 0.99 T_C) with every update variant built here, and 32 such lattices
+    batched, against the multi-spin-coded CPU baseline on this host."""
+    w = workloads.PAPER_POINT
+    N = w.L * w.L
+
+    def gpu_rate(setup):
+        lat = ising.Lattice(w.L, seed=w.seed, stream_id=w.stream_id, init=w.init,
+                            beta=1.0 / w.T, device=dev)
+        setup(lat)
+        EM = torch.empty((w.sweeps, 2), dtype=torch.int64, device=dev)
+        lat.sweep(w.sweeps, EM)
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(lat.stream)
+        for _ in range(reps):
+            lat.sweep(w.sweeps, EM)
+        b.record(lat.stream)
+        b.synchronize()
+        return round(N * w.sweeps * reps / (a.elapsed_time(b) * 1e6), 2)
+
+    rows = {"gpu_philox_on_the_fly": gpu_rate(lambda lat: None),
+            "gpu_lcg_on_the_fly": gpu_rate(lambda lat: lat.use_lcg()),
+            "gpu_pool_random_addresses": gpu_rate(lambda lat: lat.use_pool(22, False)),
+            "gpu_pool_linear": gpu_rate(lambda lat: lat.use_pool(22, True))}
+    lats = [ising.Lattice(w.L, seed=w.seed, stream_id=i, init=w.init, beta=1.0 / w.T,
+                          device=dev) for i in range(32)]
+    EMs = [torch.empty((w.sweeps, 2), dtype=torch.int64, device=dev) for _ in lats]
+    ising.multi_sweep(lats, w.sweeps, EMs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ising.multi_sweep(lats, w.sweeps, EMs)
+    torch.cuda.synchronize()
+    rows["gpu_batched_32_lattices"] = round(32 * N * w.sweeps * reps /
+                                            ((time.perf_counter() - t0) * 1e9), 2)
+    del lats, EMs
+    import baselines
+    msc = baselines.Lattice(w.L, seed=w.seed, stream_id=w.stream_id, init=w.init)
+    msc.sweeps(1.0 / w.T, 2, record=True)
+    t0 = time.perf_counter()
+    msc.sweeps(1.0 / w.T, w.sweeps, record=True)
+    rows["cpu_msc_all_cores"] = round(N * w.sweeps / ((time.perf_counter() - t0) * 1e9), 3)
+    one = baselines.Lattice(w.L, seed=w.seed, stream_id=w.stream_id, init=w.init, threads=1)
+    t0 = time.perf_counter()
+    one.sweeps(1.0 / w.T, 20, record=True)
+    rows["cpu_msc_1_core"] = round(N * 20 / ((time.perf_counter() - t0) * 1e9), 3)
+    return {"workload": "%dx%d, T = 0.99 T_C = %.6f, hot start, %d sweeps per run with per-sweep "
+                        "E/M" % (w.L, w.L, w.T, w.sweeps),
+            "unit": "spin updates/ns", "rows": rows,
+            "cpu_cores": int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()}
+
+
 def bench_fss_proof(torch, ising, dev, sweeps=200_000, discard=20_000, nblocks=20):
     """The paper's proof of concept (section 2): Binder cumulants of small
     lattices (L = 8..64, six temperatures in [2.15, 2.40], long runs on the
@@ -467,10 +526,27 @@ def cpu_baseline(w, sweeps):
     oracle.sweeps(s, 1.0 / w.T, w.seed, w.stream_id, 0, sweeps, record=True)
     dt = time.perf_counter() - t0
     ups = w.L * w.L * sweeps / (dt * 1e9)
+    # the paper's benchmark point (Table 2's "CPU simple" row: one byte per
+    # spin), all cores and one core
+    p = workloads.PAPER_POINT
+    sp = oracle.init(p.L, p.seed, p.stream_id, p.init)
+    t1 = time.perf_counter()
+    oracle.sweeps(sp, 1.0 / p.T, p.seed, p.stream_id, 0, 10, record=True)
+    paper_all = p.L * p.L * 10 / ((time.perf_counter() - t1) * 1e9)
+    oracle.set_threads(1)
+    try:
+        t1 = time.perf_counter()
+        oracle.sweeps(sp, 1.0 / p.T, p.seed, p.stream_id, 10, 2, record=True)
+        paper_one = p.L * p.L * 2 / ((time.perf_counter() - t1) * 1e9)
+    finally:
+        oracle.set_threads(threads)
     return {"value": ups, "unit": "spin updates/ns", "cores": threads, "kind": "oracle",
             "sample": "%d sweeps of the %dx%d lattice (%s start, T=%r), %.1f s"
                       % (sweeps, w.L, w.L, ["cold +1", "cold -1", "hot"][w.init], w.T, dt),
-            "cpu_model": cpu_model()}
+            "cpu_model": cpu_model(),
+            "paper_point": {"workload": "%dx%d, T = 0.99 T_C, 10 sweeps (all cores), 2 sweeps "
+                                        "(one core)" % (p.L, p.L),
+                            "value": round(paper_all, 4), "value_1core": round(paper_one, 4)}}
 
 
 def main():
@@ -575,6 +651,10 @@ def main():
     if not args.no_pool:
         print("bench: plain workload with Boltzmann-pattern pools", file=sys.stderr, flush=True)
         result["pool"] = bench_pool(torch, ising, dev, w, args.steps)
+    if not args.no_table2:
+        print("bench: the paper's benchmark point (Table 2) with every variant", file=sys.stderr,
+              flush=True)
+        result["table2"] = bench_table2(torch, ising, dev)
     if args.copy_calibration:
         # a plain copy of known size: 1 GiB read + 1 GiB written
         src = torch.ones(1 << 30, dtype=torch.uint8, device=dev)
