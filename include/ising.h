@@ -286,6 +286,21 @@ ISING_API ising_status ising_set_rng(ising_t *h, int32_t kind, void *dev_state,
                                      size_t state_bytes);
 
 /* ---------------------------------------------------------------- */
+/* Test hook.                                                         */
+/* ---------------------------------------------------------------- */
+
+/*
+ * Barrier perturbation for race tests (process-wide; 0 turns it off, the
+ * default).  With a nonzero seed, the kernels that rely on block barriers
+ * inside a launch (the LDS-resident small-lattice sweeps and the packed
+ * persistent batched kernel) make every wave pause a pseudo-random time,
+ * drawn from the seed, before each such barrier.  Results must not change;
+ * a difference points at a missing barrier.  Applies to launches enqueued
+ * after the call.  Always ISING_OK.
+ */
+ISING_API ising_status ising_debug_perturb(uint32_t seed);
+
+/* ---------------------------------------------------------------- */
 /* Finite-size-scaling analysis of per-sweep (E, M) series.           */
 /* ---------------------------------------------------------------- */
 

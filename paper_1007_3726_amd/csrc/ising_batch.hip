@@ -219,6 +219,7 @@ static ising_status run_packed(ising_lattice* const* hs, const std::vector<int>&
     std::memset(&lat[j], 0, sizeof(BatchLattice));
     lat[j].ta = targs[i];
     lat[j].ta.t = (uint32_t)hs[i]->sweep;
+    lat[j].ta.perturb = debug_perturb_seed();
     lat[j].EM = dev_EM ? dev_EM[i] : nullptr;
     lat[j].nsweeps = nsw ? nsw[i] : n;
   }

@@ -58,6 +58,22 @@ __device__ __forceinline__ void block_sum2(uint32_t a32, uint32_t p32, uint64_t*
   }
 }
 
+// Test hook: with a nonzero seed, this wave pauses for a pseudo-random
+// 0 .. 31 short sleeps (hash of seed, call site, block and wave) before a
+// block barrier.  Waves then reach the barrier in a shuffled order; a
+// result that depends on that order (a missing barrier or fence) changes.
+__device__ __forceinline__ void perturb_wave(uint32_t seed, uint32_t site) {
+  if (seed == 0) return;
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  uint32_t h = seed ^ (site * 0x9E3779B9u) ^ (blockIdx.x * 0x85EBCA77u) ^ (wave * 0xC2B2AE3Du);
+  h ^= h >> 16;
+  h *= 0x7FEB352Du;
+  h ^= h >> 15;
+  h *= 0x846CA68Bu;
+  h ^= h >> 16;
+  for (uint32_t i = 0, n = h & 31u; i < n; ++i) __builtin_amdgcn_s_sleep(8);
+}
+
 // Contribution of one updated colour-1 word to the bond and spin counts:
 // every bond has exactly one colour-1 end, so summing the anti-aligned
 // neighbours of all colour-1 sites counts each anti-aligned bond once;
@@ -217,6 +233,7 @@ __global__ __launch_bounds__(1024) void k_small_sweeps(SmallArgs a) {
         self[idx] = s_new;
         if (c == 1) count_word(s_new, n, valid, anti, up);
       }
+      perturb_wave(a.perturb, (uint32_t)(2 * k + c));
       __syncthreads();
     }
     if (a.EM) {
@@ -302,6 +319,7 @@ __global__ __launch_bounds__(1024) void k_small_sweeps_split(SmallArgs a) {
           if (c == 1) count_word(s_new, n, valid, anti, up);
         }
       }
+      perturb_wave(a.perturb, (uint32_t)(2 * k + c));
       __syncthreads();
     }
     if (a.EM) {
@@ -453,6 +471,7 @@ __device__ __forceinline__ void process_tile(const TileArgs& a, const TileLane& 
       }
     }
   }
+  perturb_wave(a.perturb, (uint32_t)(4 * tidx + 2 * colour));
   __syncthreads();
   for (int j = 0; j < RPW; ++j) {
     const int r_l = (wave * RPW + j) * R + r_off;
@@ -491,6 +510,7 @@ __device__ __forceinline__ void process_tile(const TileArgs& a, const TileLane& 
     self[y * g.W + w] = s_new;
     if (colour == 1 && em) count_word(s_new, n, valid, anti, up);
   }
+  perturb_wave(a.perturb, (uint32_t)(4 * tidx + 2 * colour + 1));
   __syncthreads();
 }
 

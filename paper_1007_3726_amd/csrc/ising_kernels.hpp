@@ -26,6 +26,7 @@ struct SmallArgs {
   uint32_t k0, k1, sid4, t0, t4, t8;
   int64_t n;            // sweeps
   int64_t* EM;          // n x 2, or null
+  uint32_t perturb;     // test hook: nonzero seeds pauses before block barriers
 };
 
 // Tiled half-sweep (L % 8 == 0): a workgroup of four waves handles a tile
@@ -74,6 +75,10 @@ struct TileArgs {
   const uint64_t* pool;
   uint32_t pool_shift, pool_mask;
   int32_t pool_linear;
+  // test hook of the LDS-staged tiles (packed persistent kernel): a nonzero
+  // seed makes every wave pause a pseudo-random time before each block
+  // barrier, so that a missing barrier shows up as a different result
+  uint32_t perturb;
 };
 
 // Switch tile arguments of a lattice to the flat mapping (see

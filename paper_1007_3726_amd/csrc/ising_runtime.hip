@@ -1,6 +1,7 @@
 // Host runtime of the C ABI declared in include/ising.h: handle lifecycle,
 // argument validation, Metropolis thresholds, launch selection, and the
 // conversion between the packed device layout and int8 host spins.
+#include <atomic>
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -243,6 +244,7 @@ ising_status enqueue_sweeps(ising_lattice* h, int64_t n, int64_t* dev_EM) {
     a.t8 = h->t8;
     a.n = n;
     a.EM = dev_EM;
+    a.perturb = debug_perturb_seed();
     int threads = (int)std::min<int64_t>(1024, ((h->plane_words + 63) / 64) * 64);
     hipError_t e = launch_small_sweeps(h->stream, a, threads);
     if (e != hipSuccess) return hip_fail(e, "small-lattice sweep launch");
@@ -312,6 +314,12 @@ static void unpack_row(const uint64_t* p0, const uint64_t* p1, int64_t L, int64_
 }  // namespace ising
 
 using namespace ising;
+
+static std::atomic<uint32_t> g_perturb_seed{0};
+
+namespace ising {
+uint32_t debug_perturb_seed() { return g_perturb_seed.load(std::memory_order_relaxed); }
+}  // namespace ising
 
 extern "C" {
 
@@ -389,6 +397,12 @@ ising_status ising_set_beta(ising_t* h, double beta) {
   h->l8 = lcg_threshold(beta, 8);
   h->beta_set = true;
   if (h->pool) return fill_pool(h);  // the patterns encode this temperature
+  return ISING_OK;
+}
+
+ising_status ising_debug_perturb(uint32_t seed) {
+  clear_error();
+  g_perturb_seed.store(seed, std::memory_order_relaxed);
   return ISING_OK;
 }
 

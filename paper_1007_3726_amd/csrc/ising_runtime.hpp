@@ -37,6 +37,8 @@ Geom make_geom(int64_t L);
 uint32_t metropolis_threshold(double beta, int dE);
 uint32_t lcg_threshold(double beta, int dE);
 int grid_blocks(int64_t work_items, int threads, int max_blocks);
+// Seed of the barrier-perturbation test hook (0: off; ising_debug_perturb).
+uint32_t debug_perturb_seed();
 
 }  // namespace ising
 

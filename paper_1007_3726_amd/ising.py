@@ -113,6 +113,7 @@ def lib():
         "ising_server_destroy": ([vp], i32),
         "ising_lcg_bytes": ([i64], ctypes.c_size_t),
         "ising_pool_bytes": ([i32], ctypes.c_size_t),
+        "ising_debug_perturb": ([u32], i32),
         "ising_set_rng": ([vp, i32, vp, ctypes.c_size_t], i32),
         "ising_reweight": ([i32, P(vp), P(i64), P(i64), P(ctypes.c_double), i32, P(i32),
                             P(ctypes.c_double), i32, vp, vp, vp], i32),
@@ -160,6 +161,12 @@ def ising_lattice_bytes(L: int) -> int:
 
 def ising_lcg_bytes(L: int) -> int:
     return int(lib().ising_lcg_bytes(L))
+
+
+def debug_perturb(seed: int) -> None:
+    """Barrier-perturbation test hook (0: off): waves pause pseudo-randomly
+    before the block barriers of the LDS-resident and packed kernels."""
+    check(lib().ising_debug_perturb(seed))
 
 
 def ising_pool_bytes(log2_patterns: int) -> int:
