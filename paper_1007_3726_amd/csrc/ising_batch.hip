@@ -124,6 +124,10 @@ static ising_status run_fused(ising_lattice* const* hs, const std::vector<int>& 
     FusedLattice& F = lat[j];
     std::memset(&F, 0, sizeof(F));
     F.ta = targs[i];
+    // lattices of 2^16 words per plane or more (4096^2 and up) take four
+    // row groups per wave: fewer tile prologues per word, and still >= 64
+    // tiles each; smaller ones keep the finer tiles of the plan
+    if (F.ta.plane_words >= (int64_t)1 << 16) F.ta.RPW = 4;
     make_flat(F.ta, true);  // the fused kernel uses the flat mapping for every lattice
     F.ta.t = (uint32_t)hs[i]->sweep;
     F.EM = dev_EM ? dev_EM[i] : nullptr;
@@ -134,6 +138,7 @@ static ising_status run_fused(ising_lattice* const* hs, const std::vector<int>& 
     for (int64_t t = 0; t < F.ntiles; ++t) tiles.push_back(FusedTile{j, (int32_t)t});
   }
   const int64_t ntiles = (int64_t)tiles.size();
+  blocks = (int)std::min<int64_t>(blocks, std::max<int64_t>(ntiles, 1));
   const size_t off_k = 0;
   const size_t off_lat = 256;
   const size_t off_tiles = align_up(off_lat + nl * sizeof(FusedLattice), 256);
@@ -268,7 +273,8 @@ ising_status batch_sweeps(ising_lattice* const* hs, int32_t count, int64_t n,
     // 2^32 words or more (L >= 741456) take the plain path
     if (tile_args(hs[i], &ta) && hs[i]->plane_words < (1ll << 32)) {
       // fine tiles balance best across the flat list; lattices with many
-      // tiles take two row groups per wave (less staging per word)
+      // tiles take two row groups per wave (the packed kernel's LDS
+      // staging bounds the shape; run_fused coarsens the largest further)
       ta.RPW = 1;
       int64_t TR = 4 * (int64_t)ta.R;
       if (((hs[i]->L + TR - 1) / TR) * ta.segs >= 256 &&
