@@ -72,6 +72,17 @@ def test_mixed_sizes_match_plain(I, form, graph_chunk):
     _batched_vs_plain(I, MIXED, 24, chunks=2, form=form, graph_chunk=graph_chunk)
 
 
+@pytest.mark.parametrize("specs", [
+    [(4096, 2.269185, 11, 3, workloads.INIT_HOT)],  # alone: the plain path
+    [(4096, 2.269185, 11, 3, workloads.INIT_HOT), (6, 2.0, 1, 1, 2)],  # with an untiled one
+    [(4096, 2.2, 11, 3, workloads.INIT_HOT), (4096, 2.3, 12, 4, workloads.INIT_HOT),
+     (64, 2.5, 1, 5, 2)],  # coarse fused tiles beside fine ones
+])
+def test_cost_model_routes_large_lattices(I, specs):
+    _say("case routing %r" % ([s[0] for s in specs],))
+    _batched_vs_plain(I, specs, 10, chunks=2)
+
+
 @pytest.mark.parametrize("form", ["fused", "packed"])
 def test_single_large_lattice(I, form):
     specs = [(4096, 2.269185, 11, 3, workloads.INIT_HOT)]
