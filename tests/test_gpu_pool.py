@@ -108,3 +108,21 @@ def test_argument_checks(I):
     EM = torch.empty((2, 2), dtype=torch.int64, device="cuda")
     with pytest.raises(I.IsingError):
         I.multi_sweep([lat2], 2, [EM])  # batched path: Philox only
+
+
+@pytest.mark.parametrize("linear", [False, True])
+def test_without_series_and_from_a_set_counter(I, linear):
+    L, beta, m, t0 = 136, 1 / 2.269185, 11, (1 << 32) - 9
+    lat = I.Lattice(L, seed=4, stream_id=2, init=workloads.INIT_HOT, beta=beta)
+    lat.use_pool(m, linear)
+    lat.sweep_count = t0
+    lat.sweep(5)  # no (E, M) series
+    em = lat.sweep_em(3).cpu().numpy()
+    s = oracle.init(L, 4, 2, workloads.INIT_HOT)
+    oracle.pool_sweeps(s, beta, 4, 2, t0, 5, m, linear, record=False)
+    oem = oracle.pool_sweeps(s, beta, 4, 2, t0 + 5, 3, m, linear)
+    assert np.array_equal(em, oem)
+    assert np.array_equal(lat.get_spins(), s)
+    assert lat.measure() == (int(oem[-1, 0]), int(oem[-1, 1]))
+    with pytest.raises(I.IsingError):  # the counter would pass 2^32 - 1
+        lat.sweep(2)
