@@ -104,3 +104,18 @@ def test_tuning_table_roundtrip(L):
     ising.tuning_set([e2])
     assert ising.tuning_lookup(9000)["rpw"] == 4 and ising.tuning_lookup(9000)["L_min"] == 8192
     ising.tuning_clear()
+
+
+def test_missing_library_fails_loudly():
+    """Without libising.so the binding raises: there is no CPU fallback."""
+    import subprocess
+    import sys
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "from paper_1007_3726_amd import ising\n"
+            "ising.LIB_PATH = '/nonexistent/libising.so'\n"
+            "try:\n"
+            "    ising.Lattice(64, beta=0.4, device='cpu')\n"
+            "except RuntimeError as e:\n"
+            "    print('raised:', e)\n" % ROOT)
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert "raised:" in r.stdout and "no fallback" in r.stdout, r.stdout + r.stderr
