@@ -119,16 +119,16 @@ static ising_status run_fused(ising_lattice* const* hs, const std::vector<int>& 
   std::vector<FusedLattice> lat(nl);
   std::vector<FusedTile> tiles;
   bool any_em = false;
+  // Every lattice keeps the tile shape of the plan.  The grid walks the
+  // tile list with a static stride, so tiles of equal size balance it;
+  // coarser tiles for the largest lattices helped a batch made mostly of
+  // them (+1.9 % on the 224-lattice grid) but unbalanced served mixes
+  // (throughput -3 %, p50 latency 1.7 -> 3.0 s).
   for (int j = 0; j < nl; ++j) {
     const int i = idx[j];
     FusedLattice& F = lat[j];
     std::memset(&F, 0, sizeof(F));
     F.ta = targs[i];
-    // lattices of 2^16 words per plane or more (4096^2 and up) take four
-    // row groups per wave: fewer tile prologues per word (a lone one takes
-    // the plain path instead, see batch_sweeps); smaller ones keep the
-    // finer tiles of the plan
-    if (F.ta.plane_words >= (int64_t)1 << 16) F.ta.RPW = 4;
     make_flat(F.ta, true);  // the fused kernel uses the flat mapping for every lattice
     F.ta.t = (uint32_t)hs[i]->sweep;
     F.EM = dev_EM ? dev_EM[i] : nullptr;
@@ -275,7 +275,7 @@ ising_status batch_sweeps(ising_lattice* const* hs, int32_t count, int64_t n,
     if (tile_args(hs[i], &ta) && hs[i]->plane_words < (1ll << 32)) {
       // fine tiles balance best across the flat list; lattices with many
       // tiles take two row groups per wave (the packed kernel's LDS
-      // staging bounds the shape; run_fused coarsens the largest further)
+      // staging bounds the shape)
       ta.RPW = 1;
       int64_t TR = 4 * (int64_t)ta.R;
       if (((hs[i]->L + TR - 1) / TR) * ta.segs >= 256 &&
