@@ -119,11 +119,9 @@ static ising_status run_fused(ising_lattice* const* hs, const std::vector<int>& 
   std::vector<FusedLattice> lat(nl);
   std::vector<FusedTile> tiles;
   bool any_em = false;
-  // Every lattice keeps the tile shape of the plan.  The grid walks the
-  // tile list with a static stride, so tiles of equal size balance it;
-  // coarser tiles for the largest lattices helped a batch made mostly of
-  // them (+1.9 % on the 224-lattice grid) but unbalanced served mixes
-  // (throughput -3 %, p50 latency 1.7 -> 3.0 s).
+  // Every lattice keeps the tile shape of the plan (coarser tiles for the
+  // largest lattices helped a batch made mostly of them, +1.9 % on the
+  // 224-lattice grid, but unbalanced served mixes: p50 latency 1.7 -> 3.0 s).
   for (int j = 0; j < nl; ++j) {
     const int i = idx[j];
     FusedLattice& F = lat[j];
@@ -133,10 +131,24 @@ static ising_status run_fused(ising_lattice* const* hs, const std::vector<int>& 
     F.ta.t = (uint32_t)hs[i]->sweep;
     F.EM = dev_EM ? dev_EM[i] : nullptr;
     any_em = any_em || F.EM != nullptr;
-    F.first_tile = (int64_t)tiles.size();
     F.ntiles = F.ta.tiles;
     F.nsweeps = nsw ? nsw[i] : n;
-    for (int64_t t = 0; t < F.ntiles; ++t) tiles.push_back(FusedTile{j, (int32_t)t});
+  }
+  // The grid deals the tile list out with a static stride.  Listing the
+  // larger tiles first (two row groups per wave before one), and within a
+  // size the lattices that run the most sweeps of this launch first, gives
+  // every workgroup about the same work per round (longest first), and the
+  // tiles of lattices that finish early in a chunk drop out of the end of
+  // the list.  Results do not depend on the order.
+  std::vector<int> order(nl);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    if (lat[a].ta.RPW != lat[b].ta.RPW) return lat[a].ta.RPW > lat[b].ta.RPW;
+    return lat[a].nsweeps > lat[b].nsweeps;
+  });
+  for (int j : order) {
+    lat[j].first_tile = (int64_t)tiles.size();
+    for (int64_t t = 0; t < lat[j].ntiles; ++t) tiles.push_back(FusedTile{j, (int32_t)t});
   }
   const int64_t ntiles = (int64_t)tiles.size();
   blocks = (int)std::min<int64_t>(blocks, std::max<int64_t>(ntiles, 1));
