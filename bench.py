@@ -78,7 +78,7 @@ def parse():
                    help="requests of the 2000-request Poisson stream to serve (default: the "
                         "first 200, about 20 s)")
     p.add_argument("--served-arena-gib", type=float, default=1.0)
-    p.add_argument("--served-quantum", type=int, default=200)
+    p.add_argument("--served-quantum", type=int, default=400)
     p.add_argument("--plain-fifo-requests", type=int, default=20,
                    help="requests of the same stream run one by one with the plain path")
     return p.parse_args()
