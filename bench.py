@@ -552,7 +552,7 @@ def cpu_baseline(w, sweeps):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (each lattice is held whole by one "
+        print("bench.py: the benchmark runs on one GPU only (each lattice is held whole by one "
               "MI355X); --gpus %d is not supported" % args.gpus, file=sys.stderr)
         sys.exit(2)
     import torch
