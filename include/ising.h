@@ -73,6 +73,7 @@ typedef int32_t ising_status;
 
 typedef struct ising_lattice ising_t;
 typedef struct ising_server ising_server_t;
+typedef struct ising_strip ising_strip_t;
 
 /* Thread-local text of the last failure in this thread ("" if none). */
 ISING_API const char *ising_last_error(void);
@@ -284,6 +285,80 @@ ISING_API size_t ising_pool_bytes(int32_t log2_patterns);
  */
 ISING_API ising_status ising_set_rng(ising_t *h, int32_t kind, void *dev_state,
                                      size_t state_bytes);
+
+/* ---------------------------------------------------------------- */
+/* Row-strip shares: one GPU's part of a multi-GPU decomposition.      */
+/* ---------------------------------------------------------------- */
+
+/*
+ * Section 6 splits one lattice over several GPUs; each updates its own
+ * part and exchanges border rows with its neighbours between the two
+ * colour steps of a sweep (B only after all of A, section 3).  A strip is
+ * the rows y0 .. y0 + rows - 1 of an L x L lattice (L % 128 == 0) held with
+ * one halo row above (global row y0 - 1 mod L) and below (y0 + rows mod L)
+ * in each colour plane.  Uniforms are keyed by global (x, y) exactly as in
+ * ising_sweep, so strips that tile the lattice, stepped colour by colour
+ * with a halo exchange after each step, reproduce the whole lattice's
+ * spins and (E, M) bit for bit.
+ *
+ * Device bytes of a strip of `rows` rows (planes of (rows + 2) x L/128
+ * words plus per-block partials); 0 for an unsupported shape (L % 128 != 0,
+ * L outside [128, 2^21], rows outside [1, L], rows * L / 128 > 2^31).
+ */
+ISING_API size_t ising_strip_bytes(int64_t L, int64_t rows);
+
+/*
+ * Create a strip in dev_buf (caller-owned, >= ising_strip_bytes, 8-byte
+ * aligned) and initialise its own rows (init as in ising_create, keyed by
+ * global coordinates) on hip_stream.  The halos are undefined until the
+ * first exchange of each colour.  EINVAL / ENOMEM / EDEVICE.
+ */
+ISING_API ising_status ising_strip_create(int64_t L, int64_t y0, int64_t rows, uint64_t seed,
+                                          uint32_t stream_id, int32_t init, void *dev_buf,
+                                          size_t dev_bytes, void *hip_stream,
+                                          ising_strip_t **out);
+ISING_API ising_status ising_strip_destroy(ising_strip_t *h);
+/* Thresholds as ising_set_beta. */
+ISING_API ising_status ising_strip_set_beta(ising_strip_t *h, double beta);
+
+/*
+ * One colour step (0 or 1) of sweep `sweep` on the strip's own rows,
+ * reading the other colour's halos (which must hold the neighbours' rows
+ * of that colour as they are after the previous colour step).  For colour
+ * 1, dev_counts (2 int64 on the device, or NULL) receives the strip's
+ * anti-aligned bonds A (each bond counted at its colour-1 end, halo
+ * neighbours included) and up spins P; the lattice's E = 2 sum A - 2 L^2,
+ * M = 2 sum P - L^2 (ising_strip_combine).  Asynchronous on the strip's
+ * stream.
+ */
+ISING_API ising_status ising_strip_step(ising_strip_t *h, int32_t colour, uint32_t sweep,
+                                        int64_t *dev_counts);
+
+/*
+ * In-process halo exchange of colour `colour` among strips that tile the
+ * lattice in order (strip k starts where strip k-1 ends, the first at row
+ * 0, the last ending at row L; one stream): each strip's halo above
+ * receives the last row of the strip above, its halo below the first row
+ * of the strip below (periodically).  Call after every colour step with
+ * that colour, and once per colour after creation.  Across GPUs the same
+ * rows move by RCCL send/recv (ising_strip_row gives their addresses).
+ */
+ISING_API ising_status ising_strip_exchange(ising_strip_t *const *hs, int32_t count,
+                                            int32_t colour);
+
+/* Device address and size of one row of colour `colour`: which 0 = halo
+ * above, 1 = first own row, 2 = last own row, 3 = halo below. */
+ISING_API ising_status ising_strip_row(const ising_strip_t *h, int32_t colour, int32_t which,
+                                       void **ptr, size_t *bytes);
+
+/* The strip's own rows as int8 (+1 / -1), rows x L row-major (synchronous). */
+ISING_API ising_status ising_strip_get_rows(ising_strip_t *h, int8_t *host);
+
+/* EM[k] = (2 sum_s A - 2 L^2, 2 sum_s P - L^2) for k < n from dev_counts laid
+ * out [n][nstrips][2] (the per-sweep all-reduce of the strips' counts), on
+ * hip_stream. */
+ISING_API ising_status ising_strip_combine(const int64_t *dev_counts, int32_t nstrips, int64_t n,
+                                           int64_t L, int64_t *dev_EM, void *hip_stream);
 
 /* ---------------------------------------------------------------- */
 /* Test hook.                                                         */

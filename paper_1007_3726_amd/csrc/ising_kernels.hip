@@ -788,6 +788,178 @@ __global__ __launch_bounds__(256) void k_pool_sweep(TileArgs a) {
 }
 
 // ---------------------------------------------------------------------
+// Strip shares (ShareArgs): the rows of one GPU's share of a row-strip
+// decomposition, with halo rows supplied by the exchange.  Words are
+// mapped flat over the strip's own rows, one word per lane per step of a
+// grid-stride loop; the uniforms are keyed by global coordinates, so a set
+// of strips advanced in step with halo exchanges reproduces the whole
+// lattice bit for bit.
+// ---------------------------------------------------------------------
+__device__ __forceinline__ void share_word(const ShareArgs& a, uint32_t i, uint32_t& r,
+                                           uint32_t& w) {
+  if (a.W == 1) {
+    r = i;
+    w = 0;
+    return;
+  }
+  uint32_t q = (uint32_t)(((uint64_t)i * a.wdiv_m) >> 32);
+  int64_t rem = (int64_t)i - (int64_t)q * a.W;
+  if (rem < 0) {
+    q -= 1u;
+    rem += a.W;
+  }
+  r = q;
+  w = (uint32_t)rem;
+}
+
+__global__ __launch_bounds__(256) void k_share_init(ShareArgs a, int init) {
+  const int64_t words = a.rows * a.W;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < 2 * words;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int c = i >= words ? 1 : 0;
+    const uint32_t j = (uint32_t)(i - c * words);
+    uint32_t r, w;
+    share_word(a, j, r, w);
+    uint64_t word;
+    if (init == 0) {
+      word = ~0ull;
+    } else if (init == 1) {
+      word = 0;
+    } else {
+      const uint64_t g = (uint64_t)(a.y0 + r) * a.L8 + 16u * w;
+      uint64_t m, unused;
+      masks_shift<true>((uint32_t)g, (uint32_t)(g >> 32), 16, a.k0, a.k1, 0u,
+                        a.sid4 | (2u + (uint32_t)c), 0x80000000u, 0x80000000u, m, unused);
+      word = m;
+    }
+    a.planes[(int64_t)c * a.plane_words + ((int64_t)r + 1) * a.W + w] = word;
+  }
+}
+
+template <int C, bool EM>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_share_sweep(
+    ShareArgs a) {
+  __shared__ uint64_t red[8];
+  uint64_t* __restrict__ self = a.planes + (C ? a.plane_words : 0);
+  const uint64_t* __restrict__ other = a.planes + (C ? 0 : a.plane_words);
+  const int64_t W = a.W;
+  const uint32_t words = (uint32_t)(a.rows * W);  // < 2^32 (checked on the host)
+  const uint32_t ctr3 = a.sid4 | (uint32_t)C;
+  uint32_t anti = 0, up = 0;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < words;
+       i += gridDim.x * blockDim.x) {
+    uint32_t r, w;
+    share_word(a, i, r, w);
+    const int64_t y = a.y0 + r;  // global row
+    const int64_t row = (int64_t)r + 1;  // buffer row; rows 0 and rows + 1 are halos
+    const bool left = ((y + C) & 1) == 0;
+    const uint32_t ws = left ? (w > 0 ? w - 1 : (uint32_t)W - 1) : (w + 1 < (uint32_t)W ? w + 1 : 0);
+    const uint64_t s = self[row * W + w];
+    const uint64_t n0 = other[row * W + w];
+    const uint64_t n2 = other[(row - 1) * W + w];
+    const uint64_t n3 = other[(row + 1) * W + w];
+    const uint64_t sd = other[row * W + ws];
+    const uint64_t g = (uint64_t)y * a.L8 + 16u * w;
+    uint64_t r4, r8;
+    masks_shift<true>((uint32_t)g, (uint32_t)(g >> 32), 16, a.k0, a.k1, a.t, ctr3, a.t4, a.t8,
+                      r4, r8);
+    __builtin_amdgcn_sched_barrier(0);
+    Nbr n;
+    n.n0 = n0;
+    n.n2 = n2;
+    n.n3 = n3;
+    n.n1 = left ? ((n0 << 1) | (sd >> 63)) : ((n0 >> 1) | (sd << 63));
+    const uint64_t s_new = s ^ flip_mask(s, n, r4, r8);
+    __hip_atomic_store(&self[row * W + w], s_new, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (C == 1 && EM) count_word(s_new, n, ~0ull, anti, up);
+  }
+  if (C == 1 && EM) {
+    uint64_t sa, sp;
+    block_sum2(anti, up, red, sa, sp);
+    if (threadIdx.x == 0) {
+      a.part[2 * blockIdx.x] = sa;
+      a.part[2 * blockIdx.x + 1] = sp;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_share_counts(const uint64_t* part, int blocks,
+                                                      int64_t* counts) {
+  __shared__ uint64_t red[8];
+  uint64_t a = 0, p = 0;
+  for (int i = threadIdx.x; i < blocks; i += blockDim.x) {
+    a += part[2 * i];
+    p += part[2 * i + 1];
+  }
+  uint64_t sa, sp;
+  // per-thread sums fit 32 bits only per block, so reduce in 64 bits here
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    a += __shfl_xor(a, off, 64);
+    p += __shfl_xor(p, off, 64);
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) {
+    red[2 * wave] = a;
+    red[2 * wave + 1] = p;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    sa = sp = 0;
+    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) {
+      sa += red[2 * k];
+      sp += red[2 * k + 1];
+    }
+    counts[0] = (int64_t)sa;
+    counts[1] = (int64_t)sp;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_share_combine(const int64_t* counts, int32_t nstrips,
+                                                       int64_t n, int64_t L, int64_t* EM) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    int64_t A = 0, P = 0;
+    for (int32_t s = 0; s < nstrips; ++s) {
+      A += counts[2 * (k * nstrips + s)];
+      P += counts[2 * (k * nstrips + s) + 1];
+    }
+    EM[2 * k] = 2 * A - 2 * L * L;
+    EM[2 * k + 1] = 2 * P - L * L;
+  }
+}
+
+hipError_t launch_share_init(hipStream_t st, const ShareArgs& a, int init) {
+  const int64_t blocks = std::min<int64_t>((2 * a.rows * a.W + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_share_init, dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(256), 0, st,
+                     a, init);
+  return hipGetLastError();
+}
+
+hipError_t launch_share_sweep(hipStream_t st, int colour, const ShareArgs& a, int blocks) {
+  if (colour == 0)
+    hipLaunchKernelGGL((k_share_sweep<0, false>), dim3(blocks), dim3(256), 0, st, a);
+  else if (a.part)
+    hipLaunchKernelGGL((k_share_sweep<1, true>), dim3(blocks), dim3(256), 0, st, a);
+  else
+    hipLaunchKernelGGL((k_share_sweep<1, false>), dim3(blocks), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_share_counts(hipStream_t st, const uint64_t* part, int blocks, int64_t* counts) {
+  hipLaunchKernelGGL(k_share_counts, dim3(1), dim3(256), 0, st, part, blocks, counts);
+  return hipGetLastError();
+}
+
+hipError_t launch_share_combine(hipStream_t st, const int64_t* counts, int32_t nstrips, int64_t n,
+                                int64_t L, int64_t* EM) {
+  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 1024);
+  hipLaunchKernelGGL(k_share_combine, dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(256), 0,
+                     st, counts, nstrips, n, L, EM);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------
 // Strip form of the wide half-sweep: one wave owns 64 consecutive words of
 // RPW consecutive rows (a "task") and walks down them, keeping the other
 // colour's rows y-1, y, y+1 in registers and loading row y+2, the

@@ -149,6 +149,30 @@ hipError_t launch_fused_finalize(hipStream_t st, const FusedArgs& f, int blocks)
 hipError_t launch_advance(hipStream_t st, uint32_t* kbase, uint32_t by);
 hipError_t launch_batch(hipStream_t st, const BatchArgs& a, int blocks);
 
+// One GPU's share of a lattice split into row strips (the per-GPU part of
+// a multi-GPU decomposition): global rows y0 .. y0 + rows - 1 of an L x L
+// lattice (L % 128 == 0, so every word is full).  Each colour plane holds
+// rows + 2 rows of W words: row 0 is the halo above (global row y0 - 1),
+// rows 1 .. rows the strip, row rows + 1 the halo below (global row
+// y0 + rows); the halos are written by the exchange, never by the kernels.
+struct ShareArgs {
+  uint64_t* planes;      // plane c at planes + c * plane_words
+  int64_t plane_words;   // (rows + 2) * W
+  int64_t rows, y0;      // strip rows, global row of the first one
+  int32_t W;             // words per row (L / 128)
+  uint32_t L8;           // L / 8: Philox blocks per colour row
+  uint32_t wdiv_m;       // floor(2^32 / W) + 1 (flat word -> row), 0 for W == 1
+  uint32_t k0, k1, sid4, t, t4, t8;
+  uint64_t* part;        // colour 1 with counts: per-block (anti-aligned bonds, up spins)
+};
+hipError_t launch_share_init(hipStream_t st, const ShareArgs& a, int init);
+hipError_t launch_share_sweep(hipStream_t st, int colour, const ShareArgs& a, int blocks);
+// counts[0..1] = sums of part[0 .. 2 blocks) (anti-aligned bonds, up spins)
+hipError_t launch_share_counts(hipStream_t st, const uint64_t* part, int blocks, int64_t* counts);
+// EM[k] = (2 sum_s A[k][s] - 2 L^2, 2 sum_s P[k][s] - L^2) for k < n, from
+// counts laid out [n][nstrips][2]
+hipError_t launch_share_combine(hipStream_t st, const int64_t* counts, int32_t nstrips, int64_t n,
+                                int64_t L, int64_t* EM);
 hipError_t launch_init(hipStream_t st, uint64_t* planes, const Geom& g, uint32_t k0, uint32_t k1,
                        uint32_t sid4, int init, int blocks);
 hipError_t launch_half_sweep(hipStream_t st, int colour, const SweepArgs& a, int blocks);

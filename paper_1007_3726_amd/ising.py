@@ -114,6 +114,16 @@ def lib():
         "ising_lcg_bytes": ([i64], ctypes.c_size_t),
         "ising_pool_bytes": ([i32], ctypes.c_size_t),
         "ising_debug_perturb": ([u32], i32),
+        "ising_strip_bytes": ([i64, i64], ctypes.c_size_t),
+        "ising_strip_create": ([i64, i64, i64, u64, u32, i32, vp, ctypes.c_size_t, vp, P(vp)],
+                               i32),
+        "ising_strip_destroy": ([vp], i32),
+        "ising_strip_set_beta": ([vp, ctypes.c_double], i32),
+        "ising_strip_step": ([vp, i32, u32, vp], i32),
+        "ising_strip_exchange": ([P(vp), i32, i32], i32),
+        "ising_strip_row": ([vp, i32, i32, P(vp), P(ctypes.c_size_t)], i32),
+        "ising_strip_get_rows": ([vp, vp], i32),
+        "ising_strip_combine": ([vp, i32, i64, i64, vp, vp], i32),
         "ising_set_rng": ([vp, i32, vp, ctypes.c_size_t], i32),
         "ising_reweight": ([i32, P(vp), P(i64), P(i64), P(ctypes.c_double), i32, P(i32),
                             P(ctypes.c_double), i32, vp, vp, vp], i32),
@@ -161,6 +171,88 @@ def ising_lattice_bytes(L: int) -> int:
 
 def ising_lcg_bytes(L: int) -> int:
     return int(lib().ising_lcg_bytes(L))
+
+
+class StripSet:
+    """A lattice split into row strips, each one GPU's share in a multi-GPU
+    decomposition, all held here on one device: every colour step runs
+    on each strip, then the halos of that colour are exchanged
+    (ising_strip_exchange stands in for RCCL send/recv between GPUs)."""
+
+    def __init__(self, L: int, nstrips: int, seed: int = 1, stream_id: int = 0,
+                 init: int = INIT_HOT, beta: Optional[float] = None, rows=None,
+                 device="cuda", stream=None):
+        import torch
+        if rows is None:
+            base, extra = divmod(L, nstrips)
+            rows = [base + (1 if k < extra else 0) for k in range(nstrips)]
+        assert len(rows) == nstrips and sum(rows) == L
+        self.L, self.rows, self.device = L, list(rows), device
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        self.bufs, self.hs = [], []
+        y0 = 0
+        for r in rows:
+            nbytes = int(lib().ising_strip_bytes(L, r))
+            if nbytes == 0:
+                raise IsingError(ISING_EINVAL, "unsupported strip shape L=%d rows=%d" % (L, r))
+            buf = _dev_alloc(nbytes, device)
+            h = ctypes.c_void_p()
+            check(lib().ising_strip_create(L, y0, r, seed, stream_id, init, buf.data_ptr(), nbytes,
+                                           _stream_ptr(self.stream), ctypes.byref(h)))
+            self.bufs.append(buf)
+            self.hs.append(h)
+            y0 += r
+        self._arr = (ctypes.c_void_p * nstrips)(*[h.value for h in self.hs])
+        for c in (0, 1):
+            check(lib().ising_strip_exchange(self._arr, nstrips, c))
+        self.t = 0
+        if beta is not None:
+            self.set_beta(beta)
+
+    def close(self):
+        for h in self.hs:
+            lib().ising_strip_destroy(h)
+        self.hs = []
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_beta(self, beta: float):
+        for h in self.hs:
+            check(lib().ising_strip_set_beta(h, beta))
+
+    def sweep_em(self, n: int):
+        """n sweeps; returns the lattice's (E, M) after each sweep as a device
+        int64 tensor (n, 2)."""
+        import torch
+        G = len(self.hs)
+        counts = torch.empty((max(n, 1), G, 2), dtype=torch.int64, device=self.device)
+        EM = torch.empty((max(n, 1), 2), dtype=torch.int64, device=self.device)
+        for k in range(n):
+            t = self.t + k
+            for c in (0, 1):
+                for s, h in enumerate(self.hs):
+                    ptr = counts[k, s].data_ptr() if c == 1 else None
+                    check(lib().ising_strip_step(h, c, t, ptr))
+                check(lib().ising_strip_exchange(self._arr, G, c))
+        check(lib().ising_strip_combine(counts.data_ptr(), G, n, self.L, EM.data_ptr(),
+                                        _stream_ptr(self.stream)))
+        self.t += n
+        return EM[:n]
+
+    def get_spins(self):
+        import numpy as np
+        out = np.empty((self.L, self.L), dtype=np.int8)
+        y0 = 0
+        for h, r in zip(self.hs, self.rows):
+            part = np.empty((r, self.L), dtype=np.int8)
+            check(lib().ising_strip_get_rows(h, part.ctypes.data))
+            out[y0:y0 + r] = part
+            y0 += r
+        return out
 
 
 def debug_perturb(seed: int) -> None:
