@@ -13,6 +13,9 @@ Also reported on the same JSON line:
   lcg, pool     - the plain workload with the paper's own random numbers:
                   per-thread LCGs, and Boltzmann-pattern pools read at random
                   addresses or linearly;
+  strip_share   - one GPU's share of 262144^2 split over 8 GPUs (a 32768-row
+                  strip with halo rows), its halo exchange, and all eight
+                  strips run here;
   table2        - the paper's benchmark point (4096^2 at 0.99 T_C) with every
                   update variant, batched, and the multi-spin CPU baseline;
   cpu_msc       - the multi-spin-coded CPU baseline (same chain, 64 spins per
@@ -68,6 +71,8 @@ def parse():
                    help="skip the multi-spin-coded CPU baseline")
     p.add_argument("--no-lcg", action="store_true",
                    help="skip the plain workload with the paper's LCG random numbers")
+    p.add_argument("--no-strip", action="store_true",
+                   help="skip the row-strip share (one GPU's part of 262144^2 over 8 GPUs)")
     p.add_argument("--no-table2", action="store_true",
                    help="skip the paper's 4096^2 benchmark point with every variant")
     p.add_argument("--no-pool", action="store_true",
@@ -444,6 +449,48 @@ def bench_table2(torch, ising, dev, reps=3):
             "cpu_cores": int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()}
 
 
+def bench_strip_share(torch, ising, dev, nstrips=8, sweeps=3):
+    """One GPU's share of the row-strip decomposition at its real shape:
+    262144^2 over 8 GPUs is eight strips of 32768 rows.  All eight run here
+    on one GPU; reported are one strip's colour-step kernel (the per-GPU
+    work), the in-process halo exchange of one colour, and the whole set's
+    rate, against the plain 262144^2 sweep."""
+    w = workloads.HUGE_T2
+    st = ising.StripSet(w.L, nstrips, seed=w.seed, stream_id=w.stream_id, init=w.init,
+                        beta=1.0 / w.T, device=dev)
+    st.sweep_em(1)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    stream = st.stream
+    ev[0].record(stream)
+    st.sweep_em(sweeps)
+    ev[1].record(stream)
+    ev[1].synchronize()
+    total_ms = ev[0].elapsed_time(ev[1])
+    # one strip's colour-0 step, then one colour's exchange
+    ev[2].record(stream)
+    ising.check(ising.lib().ising_strip_step(st.hs[0], 0, st.t, None))
+    ev[3].record(stream)
+    ev[3].synchronize()
+    step_ms = ev[2].elapsed_time(ev[3])
+    ev[2].record(stream)
+    ising.check(ising.lib().ising_strip_exchange(st._arr, nstrips, 0))
+    ev[3].record(stream)
+    ev[3].synchronize()
+    exch_ms = ev[2].elapsed_time(ev[3])
+    share_updates = (w.L // nstrips) * w.L // 2
+    out = {"workload": "%dx%d split into %d strips of %d rows (one GPU's share each), T=%r, "
+                       "hot start" % (w.L, w.L, nstrips, w.L // nstrips, w.T),
+           "share_colour_step_us": round(step_ms * 1e3, 1),
+           "share_updates_per_ns": round(share_updates / (step_ms * 1e6), 1),
+           "exchange_us_per_colour": round(exch_ms * 1e3, 1),
+           "all_strips_updates_per_ns": round(w.L * w.L * sweeps / (total_ms * 1e6), 1),
+           "halo_bytes_per_strip_per_colour": 2 * (w.L // 128) * 8}
+    del st
+    torch.cuda.empty_cache()
+    return out
+
+
 def bench_fss_proof(torch, ising, dev, sweeps=200_000, discard=20_000, nblocks=20):
     """The paper's proof of concept (section 2): Binder cumulants of small
     lattices (L = 8..64, six temperatures in [2.15, 2.40], long runs on the
@@ -651,6 +698,10 @@ def main():
     if not args.no_pool:
         print("bench: plain workload with Boltzmann-pattern pools", file=sys.stderr, flush=True)
         result["pool"] = bench_pool(torch, ising, dev, w, args.steps)
+    if not args.no_strip:
+        print("bench: one GPU's share of the row-strip decomposition", file=sys.stderr,
+              flush=True)
+        result["strip_share"] = bench_strip_share(torch, ising, dev)
     if not args.no_table2:
         print("bench: the paper's benchmark point (Table 2) with every variant", file=sys.stderr,
               flush=True)
