@@ -255,6 +255,120 @@ class StripSet:
         return out
 
 
+class DistStrip:
+    """This process's strip of an L x L lattice split over the ranks of a
+    torch.distributed group: rank r owns the r-th band of rows (as even as
+    possible).  After every colour step the boundary rows of that colour
+    move to the neighbouring ranks by point-to-point send/recv (the first
+    row up, the last row down; with the nccl backend, i.e. RCCL, straight
+    from device memory, with gloo staged through host memory), and the
+    per-sweep bond and spin counts are summed by one all-reduce.  The
+    result equals the whole lattice's bit for bit."""
+
+    def __init__(self, L: int, group=None, seed: int = 1, stream_id: int = 0,
+                 init: int = INIT_HOT, beta: Optional[float] = None, device="cuda"):
+        import torch
+        import torch.distributed as dist
+        self.group = group
+        self.world = dist.get_world_size(group)
+        self.rank = dist.get_rank(group)
+        self.host_staged = dist.get_backend(group) != "nccl"
+        base, extra = divmod(L, self.world)
+        rows = [base + (1 if k < extra else 0) for k in range(self.world)]
+        self.L, self.rows, self.y0 = L, rows[self.rank], sum(rows[:self.rank])
+        self.device = device
+        self.stream = torch.cuda.current_stream(device)
+        nbytes = int(lib().ising_strip_bytes(L, self.rows))
+        if nbytes == 0:
+            raise IsingError(ISING_EINVAL, "unsupported strip shape L=%d rows=%d" % (L, self.rows))
+        self.buf = _dev_alloc(nbytes, device)
+        self.h = ctypes.c_void_p()
+        check(lib().ising_strip_create(L, self.y0, self.rows, seed, stream_id, init,
+                                       self.buf.data_ptr(), nbytes, _stream_ptr(self.stream),
+                                       ctypes.byref(self.h)))
+        self.W = L // 128
+        self.t = 0
+        if beta is not None:
+            check(lib().ising_strip_set_beta(self.h, beta))
+        for c in (0, 1):
+            self._exchange(c)
+
+    def close(self):
+        if self.h:
+            lib().ising_strip_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_beta(self, beta: float):
+        check(lib().ising_strip_set_beta(self.h, beta))
+
+    def _row(self, colour: int, which: int):
+        ptr, nbytes = ctypes.c_void_p(), ctypes.c_size_t()
+        check(lib().ising_strip_row(self.h, colour, which, ctypes.byref(ptr), ctypes.byref(nbytes)))
+        off = ptr.value - self.buf.data_ptr()
+        return self.buf[off:off + nbytes.value]
+
+    def _exchange(self, colour: int):
+        import torch.distributed as dist
+        up = (self.rank - 1) % self.world
+        down = (self.rank + 1) % self.world
+        first, last = self._row(colour, 1), self._row(colour, 2)
+        above, below = self._row(colour, 0), self._row(colour, 3)
+        if self.host_staged:
+            first, last = first.cpu(), last.cpu()  # waits for the colour step
+            above_x, below_x = first.new_empty(first.shape), first.new_empty(first.shape)
+        else:
+            above_x, below_x = above, below
+        # Sends first (up), then last (down); receives below (from down), then
+        # above (from up).  With two ranks up and down are one peer and the
+        # messages pair off in this order (RCCL has no tags); gloo also gets
+        # tags: 1 for rows travelling up, 0 for rows travelling down.
+        ops = [dist.P2POp(dist.isend, first, up, self.group, tag=1),
+               dist.P2POp(dist.isend, last, down, self.group, tag=0),
+               dist.P2POp(dist.irecv, below_x, down, self.group, tag=1),
+               dist.P2POp(dist.irecv, above_x, up, self.group, tag=0)]
+        for req in dist.batch_isend_irecv(ops):
+            req.wait()
+        if self.host_staged:
+            above.copy_(above_x)
+            below.copy_(below_x)
+
+    def sweep_em(self, n: int):
+        """n sweeps of the whole lattice (every rank calls it); returns the
+        lattice's (E, M) after each sweep as a device int64 tensor (n, 2)."""
+        import torch
+        import torch.distributed as dist
+        counts = torch.zeros((max(n, 1), 2), dtype=torch.int64, device=self.device)
+        for k in range(n):
+            for c in (0, 1):
+                ptr = counts[k].data_ptr() if c == 1 else None
+                check(lib().ising_strip_step(self.h, c, self.t + k, ptr))
+                self._exchange(c)
+        if self.host_staged:
+            host = counts.cpu()
+            dist.all_reduce(host, group=self.group)
+            counts.copy_(host)
+        else:
+            dist.all_reduce(counts, group=self.group)
+        EM = torch.empty((max(n, 1), 2), dtype=torch.int64, device=self.device)
+        check(lib().ising_strip_combine(counts.data_ptr(), 1, n, self.L, EM.data_ptr(),
+                                        _stream_ptr(self.stream)))
+        self.t += n
+        return EM[:n]
+
+    def get_rows(self):
+        """This rank's rows as int8 (rows x L)."""
+        import numpy as np
+        out = np.empty((self.rows, self.L), dtype=np.int8)
+        check(lib().ising_strip_get_rows(self.h, out.ctypes.data))
+        return out
+
+
 def debug_perturb(seed: int) -> None:
     """Barrier-perturbation test hook (0: off): waves pause pseudo-randomly
     before the block barriers of the LDS-resident and packed kernels."""
