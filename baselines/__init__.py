@@ -36,6 +36,10 @@ def lib():
         L.msc_get_spins.argtypes = [pu64, i64, p8]
         L.msc_get_spins.restype = None
         L.msc_scalar_only.argtypes = [i32]
+        L.msc_pool_fill.argtypes = [pu64, i32, u64, u32, ctypes.c_double, i32]
+        L.msc_pool_fill.restype = i32
+        L.msc_pool_sweeps.argtypes = [pu64, i64, u64, u32, pu64, i32, i32, u32, i64, p64, i32]
+        L.msc_pool_sweeps.restype = i32
         L.msc_word_masks.argtypes = [i64, u64, u32, i64, i64, u32, u32, u32, u32, pu64]
         L.msc_word_masks.restype = None
         L.msc_scalar_only.restype = None
@@ -83,6 +87,28 @@ class Lattice:
         p = EM.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)) if record else None
         if lib().msc_sweeps(self._p(), self.L, self.seed, self.stream_id, beta, self.t, n, p,
                             self.threads) != 0:
+            raise ValueError("bad arguments")
+        self.t += n
+        return EM
+
+    def use_pool(self, beta: float, log2_patterns: int = 22, linear: bool = False):
+        """Switch to the Boltzmann-pattern-pool dynamics (the paper's CPU
+        scheme) with a pool drawn for beta; sweeps() then reads it."""
+        self.pool = np.zeros(2 << log2_patterns, dtype=np.uint64)
+        pu64 = ctypes.POINTER(ctypes.c_uint64)
+        if lib().msc_pool_fill(self.pool.ctypes.data_as(pu64), log2_patterns, self.seed,
+                               self.stream_id, beta, self.threads) != 0:
+            raise ValueError("bad pool arguments")
+        self.pool_m, self.pool_linear, self.pool_beta = log2_patterns, linear, beta
+
+    def pool_sweeps(self, n: int, record: bool = True):
+        """n sweeps of the pool dynamics (use_pool first); (n, 2) int64 (E, M)."""
+        EM = np.zeros((n, 2), dtype=np.int64) if record else None
+        p = EM.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)) if record else None
+        pu64 = ctypes.POINTER(ctypes.c_uint64)
+        if lib().msc_pool_sweeps(self._p(), self.L, self.seed, self.stream_id,
+                                 self.pool.ctypes.data_as(pu64), self.pool_m,
+                                 1 if self.pool_linear else 0, self.t, n, p, self.threads) != 0:
             raise ValueError("bad arguments")
         self.t += n
         return EM

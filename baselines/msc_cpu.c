@@ -226,6 +226,138 @@ static void row_step(const msc_ctx* x, uint64_t* planes, int64_t y, int c, uint3
   *P += p_sum;
 }
 
+/* ---- Boltzmann-pattern pools (section 4: the paper's own CPU program
+ * reads exp4 / exp8 patterns from a pool at a random address) ----
+ * The pool holds P = 2^m patterns of 64 sites, each stored here as the
+ * pair (r4, r8) = (exp4 | exp8, exp8): bit b of pattern p compares the
+ * uniform of index 64 p + b (counter (lo32, hi32 of (64 p + b) / 4,
+ * 2^32 - 1, stream_id << 2 | 2)) with t4 and t8.  In sweep t, colour c,
+ * word j = y W + w reads pattern v >> (32 - m), v = output 0 of the block
+ * with counter (lo32 j, hi32 j, t, stream_id << 2 | c); with linear reads
+ * v comes from the block of q = j / 256 and the word reads pattern
+ * ((v >> (32 - m)) + j mod 256) mod P.  The same dynamics as the GPU
+ * library's ISING_RNG_POOL / ISING_RNG_POOL_LINEAR. */
+
+/* Output 0 of the Philox block with counter (lo32 q, hi32 q, t, word3). */
+static inline uint32_t philox_x0(const msc_ctx* x, uint64_t q, uint32_t t, uint32_t word3) {
+  uint32_t c[4] = {(uint32_t)q, (uint32_t)(q >> 32), t, word3};
+  philox_block(c, x->k0, x->k1);
+  return c[0];
+}
+
+/* 2^m patterns into pool[2 p] = r4, pool[2 p + 1] = r8.  Returns 0, or -1
+ * for m outside [1, 28]. */
+int msc_pool_fill(uint64_t* pool, int m, uint64_t seed, uint32_t stream_id, double beta,
+                  int threads) {
+  if (!pool || m < 1 || m > 28 || beta < 0 || isnan(beta)) return -1;
+  msc_ctx x;
+  ctx_make(&x, 128, seed, stream_id);  /* L only sets the word geometry, unused here */
+  const uint32_t t4 = threshold(beta, 4), t8 = threshold(beta, 8);
+  const int64_t P = (int64_t)1 << m;
+  const int nt = threads > 0 ? threads : omp_get_max_threads();
+#pragma omp parallel for schedule(static) num_threads(nt)
+  for (int64_t p = 0; p < P; ++p) {
+    uint64_t r4 = 0, r8 = 0;
+    if (x.vector) {
+      masks_avx512(&x, 16u * (uint64_t)p, 0xFFFFFFFFu, 2u, t4, t8, &r4, &r8);
+    } else {
+      for (int q = 0; q < 16; ++q) {
+        uint32_t c[4] = {(uint32_t)(16 * p + q), 0u, 0xFFFFFFFFu, x.sid4 | 2u};
+        philox_block(c, x.k0, x.k1);
+        for (int j = 0; j < 4; ++j) {
+          r4 |= (uint64_t)(c[j] < t4) << (4 * q + j);
+          r8 |= (uint64_t)(c[j] < t8) << (4 * q + j);
+        }
+      }
+    }
+    pool[2 * p] = r4;
+    pool[2 * p + 1] = r8;
+  }
+  return 0;
+}
+
+static void row_step_pool(const msc_ctx* x, uint64_t* planes, int64_t y, int c, uint32_t t,
+                          const uint64_t* pool, int m, int linear, int count, int64_t* A,
+                          int64_t* P) {
+  const int64_t L = x->L, W = x->W;
+  uint64_t* self = planes + (int64_t)c * L * W + y * W;
+  const uint64_t* other = planes + (int64_t)(1 - c) * L * W;
+  const uint64_t* o0 = other + y * W;
+  const uint64_t* up = other + (y == 0 ? L - 1 : y - 1) * W;
+  const uint64_t* dn = other + (y == L - 1 ? 0 : y + 1) * W;
+  const int left = ((y + c) & 1) == 0;
+  const uint32_t word3 = x->sid4 | (uint32_t)c, mask = (uint32_t)(((uint64_t)1 << m) - 1);
+  uint64_t have_q = ~0ull;
+  uint32_t start = 0;
+  int64_t a_sum = 0, p_sum = 0;
+  for (int64_t w = 0; w < W; ++w) {
+    const int last = w == W - 1;
+    const uint64_t valid = last ? x->last_valid : ~0ull;
+    const uint64_t s = self[w], n0 = o0[w], n2 = up[w], n3 = dn[w];
+    uint64_t n1;
+    if (left) {
+      const uint64_t in = w > 0 ? (o0[w - 1] >> 63) : ((o0[W - 1] >> (x->nb_last - 1)) & 1u);
+      n1 = (n0 << 1) | in;
+    } else {
+      const uint64_t in = (last ? o0[0] : o0[w + 1]) & 1u;
+      n1 = (n0 >> 1) | (in << (last ? x->nb_last - 1 : 63));
+    }
+    const uint64_t j = (uint64_t)(y * W + w);
+    uint32_t a;
+    if (linear) {
+      if ((j >> 8) != have_q) {
+        have_q = j >> 8;
+        start = philox_x0(x, have_q, t, word3) >> (32 - m);
+      }
+      a = (start + (uint32_t)(j & 255u)) & mask;
+    } else {
+      a = philox_x0(x, j, t, word3) >> (32 - m);
+    }
+    const uint64_t r4 = pool[2 * (uint64_t)a], r8 = pool[2 * (uint64_t)a + 1];
+    const uint64_t a0 = s ^ n0, a1 = s ^ n1, a2 = s ^ n2, a3 = s ^ n3;
+    const uint64_t two_plus = (a0 & a1) | (a2 & a3) | ((a0 ^ a1) & (a2 ^ a3));
+    const uint64_t some = a0 | a1 | a2 | a3;
+    const uint64_t flip = (two_plus | (some & ~two_plus & r4) | (~some & r8)) & valid;
+    const uint64_t sn = s ^ flip;
+    self[w] = sn;
+    if (count) {
+      a_sum += __builtin_popcountll(sn ^ n0) + __builtin_popcountll((sn ^ n1) & valid) +
+               __builtin_popcountll(sn ^ n2) + __builtin_popcountll(sn ^ n3);
+      p_sum += __builtin_popcountll(sn) + __builtin_popcountll(n0);
+    }
+  }
+  *A += a_sum;
+  *P += p_sum;
+}
+
+/* n sweeps with a pool of 2^m patterns (msc_pool_fill for this beta);
+ * linear 0: an address per word, 1: linear reads per 256-word group.
+ * Returns 0, or -1 for bad arguments. */
+int msc_pool_sweeps(uint64_t* planes, int64_t L, uint64_t seed, uint32_t stream_id,
+                    const uint64_t* pool, int m, int linear, uint32_t t0, int64_t n, int64_t* EM,
+                    int threads) {
+  if (L < 4 || L % 2 || !planes || !pool || m < 1 || m > 28 || n < 0) return -1;
+  msc_ctx x;
+  ctx_make(&x, L, seed, stream_id);
+  const int nt = threads > 0 ? threads : omp_get_max_threads();
+  const int64_t N = L * L;
+  for (int64_t k = 0; k < n; ++k) {
+    const uint32_t t = t0 + (uint32_t)k;
+    for (int c = 0; c < 2; ++c) {
+      const int count = c == 1 && EM != NULL;
+      int64_t A = 0, P = 0;
+#pragma omp parallel for schedule(static) num_threads(nt) reduction(+ : A, P)
+      for (int64_t y = 0; y < L; ++y)
+        row_step_pool(&x, planes, y, c, t, pool, m, linear, count, &A, &P);
+      if (count) {
+        EM[2 * k] = 2 * A - 2 * N;
+        EM[2 * k + 1] = 2 * P - N;
+      }
+    }
+  }
+  return 0;
+}
+
 /* Bytes of the two colour planes of an L x L lattice. */
 int64_t msc_bytes(int64_t L) {
   if (L < 4 || L % 2) return 0;

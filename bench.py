@@ -443,6 +443,18 @@ def bench_table2(torch, ising, dev, reps=3):
     t0 = time.perf_counter()
     one.sweeps(1.0 / w.T, 20, record=True)
     rows["cpu_msc_1_core"] = round(N * 20 / ((time.perf_counter() - t0) * 1e9), 3)
+    # the paper's own CPU scheme: Boltzmann-pattern pool (2^22 patterns)
+    for name, linear in (("random_addresses", False), ("linear", True)):
+        msc.use_pool(1.0 / w.T, 22, linear)
+        t0 = time.perf_counter()
+        msc.pool_sweeps(w.sweeps, record=True)
+        rows["cpu_msc_pool_%s_all_cores" % name] = round(
+            N * w.sweeps / ((time.perf_counter() - t0) * 1e9), 3)
+        one.use_pool(1.0 / w.T, 22, linear)
+        t0 = time.perf_counter()
+        one.pool_sweeps(10, record=True)
+        rows["cpu_msc_pool_%s_1_core" % name] = round(
+            N * 10 / ((time.perf_counter() - t0) * 1e9), 3)
     return {"workload": "%dx%d, T = 0.99 T_C = %.6f, hot start, %d sweeps per run with per-sweep "
                         "E/M" % (w.L, w.L, w.T, w.sweeps),
             "unit": "spin updates/ns", "rows": rows,

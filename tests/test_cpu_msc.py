@@ -91,3 +91,17 @@ def test_argument_checks():
         b.sweeps(-1.0, 1)
     with pytest.raises(ValueError):
         b.sweeps(float("nan"), 1)
+
+
+@pytest.mark.parametrize("linear", [False, True])
+@pytest.mark.parametrize("L,m", [(8, 10), (24, 12), (136, 12), (200, 14), (1024, 16)])
+def test_pool_dynamics_equal_the_oracle(path, L, m, linear):
+    beta, seed, sid = 1 / 2.269185, 9, 2
+    b = baselines.Lattice(L, seed=seed, stream_id=sid, init=workloads.INIT_HOT, threads=2)
+    b.use_pool(beta, m, linear)
+    s = oracle.init(L, seed, sid, workloads.INIT_HOT)
+    for t in range(3):
+        em = b.pool_sweeps(1)
+        oem = oracle.pool_sweeps(s, beta, seed, sid, t, 1, m, linear)
+        assert np.array_equal(em, oem), t
+        assert np.array_equal(b.spins(), s), t
