@@ -3,7 +3,8 @@ section 6), run together on one GPU with the in-process halo exchange:
 they must reproduce the whole lattice's spins and per-sweep (E, M) bit for
 bit, for even and uneven splits, one strip (its own halos), and at the real
 share shape of 262144^2 over 8 GPUs (eight strips of 32768 rows, compared
-on the device with the plain 262144^2 run)."""
+on the device with the plain 262144^2 run and, in light-cone windows that
+straddle strip borders and the periodic wrap, with the oracle)."""
 import sys
 
 import numpy as np
@@ -58,6 +59,27 @@ def test_starts_and_temperatures(I, init, beta):
     assert np.array_equal(em, oem) and np.array_equal(st.get_spins(), s)
 
 
+def _strip_window(torch, st, L, x0, y0, ww, hh):
+    """Spins (+1 / -1) of the ww x hh window at (x0, y0), periodic, read from
+    the strips' packed planes: colour (x + y) & 1, own row y - y_start + 1
+    (row 0 is the halo above), bit k & 63 of word k >> 6 for k = x >> 1."""
+    W = L // 128
+    starts = np.cumsum([0] + list(st.rows))
+    out = np.empty((hh, ww), dtype=np.int8)
+    for i in range(hh):
+        y = (y0 + i) % L
+        s = int(np.searchsorted(starts, y, side="right")) - 1
+        r = st.rows[s]
+        part = st.bufs[s][: 2 * (r + 2) * W * 8].view(torch.int64).view(2, r + 2, W)
+        words = part[:, y - int(starts[s]) + 1].cpu().numpy().view(np.uint64)
+        for j in range(ww):
+            x = (x0 + j) % L
+            k = x >> 1
+            bit = (int(words[(x + y) & 1, k >> 6]) >> (k & 63)) & 1
+            out[i, j] = 1 if bit else -1
+    return out
+
+
 def test_real_share_shape(I):
     """262144^2 split over 8 GPUs: eight 32768-row strips (1 GiB each)."""
     import torch
@@ -71,6 +93,12 @@ def test_real_share_shape(I):
     lat = I.Lattice(L, seed=w.seed, stream_id=w.stream_id, init=w.init, beta=1.0 / w.T)
     ref = lat.sweep_em(n).cpu().numpy()
     assert np.array_equal(em, ref)
+    # windows across the borders of strips 0/1 and 4/5 and across the wrap 7/0
+    R = L // G
+    for (x0, y0) in [(1000, R - 6), (123456, 5 * R - 3), (L - 20, L - 6)]:
+        got = _strip_window(torch, st, L, x0, y0, 40, 12)
+        want = oracle.window(L, 1.0 / w.T, w.seed, w.stream_id, w.init, 0, n, x0, y0, 40, 12)
+        assert np.array_equal(got, want), "window at (%d, %d) differs" % (x0, y0)
     W = L // 128
     full = lat.buf[: 2 * L * W * 8].view(torch.int64).view(2, L, W)
     y0 = 0
