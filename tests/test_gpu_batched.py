@@ -159,3 +159,36 @@ def test_lattice_totals_past_2_to_the_32(I):
     assert EMp[-1, 1] > (1 << 31)  # most spins still up: the total exceeds 2^32 / 2
     for (x0, y0) in [(0, 0), (L - 40, L - 7), (L // 2, 12345)]:
         assert np.array_equal(b.get_window(x0, y0, 64, 16), p.get_window(x0, y0, 64, 16))
+
+
+def test_whole_fss_grid_against_the_oracle(I):
+    """The benchmark's 224-lattice grid (L = 64 .. 4096, 32 temperatures),
+    one multi_sweep call as the benchmark makes it.  Lattices with L <= 256
+    match a full oracle run (spins and per-sweep E/M); larger ones match the
+    oracle in light-cone windows at the periodic corner and inside, obey
+    the E/M invariants, and their last E/M equals a recount."""
+    import torch
+    grid = workloads.fss_grid()
+    assert len(grid) == 224
+    n = 40
+    _say("case whole fss grid, %d sweeps" % n)
+    lats = [I.Lattice(g.L, seed=g.seed, stream_id=g.stream_id, init=g.init, beta=1.0 / g.T)
+            for g in grid]
+    EMs = [torch.empty((n, 2), dtype=torch.int64, device="cuda") for _ in grid]
+    I.multi_sweep(lats, n, EMs)
+    torch.cuda.synchronize()
+    for g, lat, em in zip(grid, lats, EMs):
+        em = em.cpu().numpy()
+        beta = 1.0 / g.T
+        if g.L <= 256:
+            s, oEM = oracle.run(g.L, beta, g.seed, g.stream_id, g.init, n)
+            assert np.array_equal(em, oEM), g
+            assert np.array_equal(lat.get_spins(), s), g
+            continue
+        N = g.L * g.L
+        assert np.all(em[:, 0] % 4 == 0) and np.all((em[:, 1] - N) % 2 == 0), g
+        assert lat.measure() == (int(em[-1, 0]), int(em[-1, 1])), g
+        for (x0, y0) in [(g.L - 20, g.L - 6), (g.L // 3, g.L // 2 + 1)]:
+            got = lat.get_window(x0, y0, 40, 12)
+            want = oracle.window(g.L, beta, g.seed, g.stream_id, g.init, 0, n, x0, y0, 40, 12)
+            assert np.array_equal(got, want), (g, x0, y0)
