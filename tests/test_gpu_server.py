@@ -132,3 +132,39 @@ def test_rejections(I):
         srv.poll(12345)
     assert e.value.code == I.ISING_ENOTFOUND
     srv.close()
+
+
+@pytest.mark.parametrize("quantum", [12, 400])
+def test_served_stream_requests_against_the_oracle(I, quantum):
+    """The first 24 requests of the served stream (L from 32 to 8032, hot and
+    cold starts, their own temperatures, seeds and stream ids), sweeps capped
+    at 30, served together; quantum 12 makes them cross quanta, 400 is the
+    benchmark's.  L <= 256: the whole series and lattice equal the oracle's;
+    larger L: oracle light-cone windows of the returned spins, the series'
+    invariants, and the last E/M recounted from the returned spins."""
+    stream = workloads.served_stream()[:24]
+    reqs = [{"L": q.L, "beta": 1.0 / q.T, "seed": q.seed, "stream_id": q.stream_id,
+             "init": q.init, "n_sweeps": min(q.sweeps, 30), "n_discard": 0,
+             "record_series": True, "return_spins": True} for q in stream]
+    _say("case served stream prefix, quantum %d" % quantum)
+    res, stats = _run(I, reqs, 256 << 20, quantum)
+    assert stats["done"] == len(reqs)
+    for r, got in zip(reqs, res):
+        L, n = r["L"], r["n_sweeps"]
+        assert got["sweeps_done"] == n
+        if L <= 256:
+            s, oEM = oracle.run(L, r["beta"], r["seed"], r["stream_id"], r["init"], n)
+            assert np.array_equal(got["series"], oEM), r
+            assert np.array_equal(got["spins"], s), r
+            continue
+        sp = got["spins"].astype(np.int64)
+        E = -int(np.sum(sp * (np.roll(sp, -1, axis=1) + np.roll(sp, -1, axis=0))))
+        assert (got["E_final"], got["M_final"]) == (E, int(sp.sum())), r
+        assert tuple(got["series"][-1]) == (E, int(sp.sum())), r
+        assert np.all(got["series"][:, 0] % 4 == 0), r
+        for (x0, y0) in [(L - 20, L - 6), (L // 3, L // 2 + 1)]:
+            ys = (y0 + np.arange(12)) % L
+            xs = (x0 + np.arange(40)) % L
+            want = oracle.window(L, r["beta"], r["seed"], r["stream_id"], r["init"], 0, n, x0, y0,
+                                 40, 12)
+            assert np.array_equal(got["spins"][np.ix_(ys, xs)], want), (r, x0, y0)
