@@ -114,3 +114,19 @@ def test_argument_checks(I):
     with pytest.raises(I.IsingError):
         I.multi_sweep([lat2], 2, [EM])  # batched path is Philox only
     assert I.ising_lcg_bytes(64) == 2 * 64 * 1 * 4 and I.ising_lcg_bytes(7) == 0
+
+
+def test_benchmark_workload(I):
+    """16384^2 from a cold start at T = 2.269185, seed 1, as the benchmark
+    runs it: two sweeps, whole lattice, series and generator states."""
+    w = workloads.LARGE
+    n = 2
+    _say("case %s lcg, %d sweeps" % (w.name, n))
+    lat = _lcg_lattice(I, w.L, w.seed, w.init, 1.0 / w.T)
+    em = lat.sweep_em(n).cpu().numpy()
+    s = oracle.init(w.L, w.seed, w.stream_id, w.init)
+    st = oracle.lcg_seed(w.L, w.seed)
+    oem = oracle.lcg_sweeps(s, 1.0 / w.T, st, n)
+    assert np.array_equal(em, oem)
+    assert np.array_equal(lat.get_spins(), s)
+    assert np.array_equal(lat.lcg_states(), st)

@@ -126,3 +126,19 @@ def test_without_series_and_from_a_set_counter(I, linear):
     assert lat.measure() == (int(oem[-1, 0]), int(oem[-1, 1]))
     with pytest.raises(I.IsingError):  # the counter would pass 2^32 - 1
         lat.sweep(2)
+
+
+@pytest.mark.parametrize("linear", [False, True])
+def test_benchmark_workload(I, linear):
+    """16384^2 from a cold start at T = 2.269185 with the benchmark's pool of
+    2^22 patterns, both address rules: two sweeps, whole lattice and series."""
+    w = workloads.LARGE
+    n, m = 2, 22
+    _say("case %s pool m=%d linear=%s" % (w.name, m, linear))
+    lat = I.Lattice(w.L, seed=w.seed, stream_id=w.stream_id, init=w.init, beta=1.0 / w.T)
+    lat.use_pool(m, linear)
+    em = lat.sweep_em(n).cpu().numpy()
+    s = oracle.init(w.L, w.seed, w.stream_id, w.init)
+    oem = oracle.pool_sweeps(s, 1.0 / w.T, w.seed, w.stream_id, 0, n, m, linear)
+    assert np.array_equal(em, oem)
+    assert np.array_equal(lat.get_spins(), s)
