@@ -262,8 +262,9 @@ class DistStrip:
     move to the neighbouring ranks by point-to-point send/recv (the first
     row up, the last row down; with the nccl backend, i.e. RCCL, straight
     from device memory, with gloo staged through host memory), and the
-    per-sweep bond and spin counts are summed by one all-reduce.  The
-    result equals the whole lattice's bit for bit."""
+    per-sweep bond and spin counts are summed by one all-reduce.  A group of
+    one rank refreshes its halos from its own rows without any transport.
+    The result equals the whole lattice's bit for bit."""
 
     def __init__(self, L: int, group=None, seed: int = 1, stream_id: int = 0,
                  init: int = INIT_HOT, beta: Optional[float] = None, device="cuda"):
@@ -315,6 +316,9 @@ class DistStrip:
 
     def _exchange(self, colour: int):
         import torch.distributed as dist
+        if self.world == 1:  # both neighbours are this strip: its own rows, no transport
+            check(lib().ising_strip_exchange((ctypes.c_void_p * 1)(self.h.value), 1, colour))
+            return
         up = (self.rank - 1) % self.world
         down = (self.rank + 1) % self.world
         first, last = self._row(colour, 1), self._row(colour, 2)

@@ -1,6 +1,7 @@
-"""The distributed row-strip driver (DistStrip) in several processes that
-share the one GPU: gloo ranks (the halo rows staged through host memory;
-RCCL cannot put two ranks on one device), one strip per rank.  The gathered
+"""The distributed row-strip driver (DistStrip) in one to three processes
+that share the one GPU: gloo ranks (the halo rows staged through host
+memory; RCCL cannot put two ranks on one device), one strip per rank; a
+single rank exchanges with itself in place.  The gathered
 lattice and the per-sweep (E, M) must equal the oracle's whole-lattice run
 bit for bit."""
 import os
@@ -49,7 +50,7 @@ def _rank_main(rank, world, port, L, n, beta, seed, sid, out_dir):
     dist.destroy_process_group()
 
 
-@pytest.mark.parametrize("world,L", [(2, 256), (3, 384)])
+@pytest.mark.parametrize("world,L", [(1, 128), (2, 256), (3, 384)])
 def test_distributed_strips_on_one_gpu(tmp_path, world, L):
     import torch
     import torch.multiprocessing as mp
