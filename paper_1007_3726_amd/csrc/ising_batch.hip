@@ -303,7 +303,7 @@ ising_status batch_sweeps(ising_lattice* const* hs, int32_t count, int64_t n,
     }
   }
   // one large lattice alone runs faster on the plain path (its own tuned
-  // shape, no tile table): 4096^2 1366 against 1140 updates/ns fused
+  // shape, no tile table): 4096^2 1345-1366 against 1140 updates/ns fused
   if (opt.force_form < 0 && tiled.size() == 1 && hs[tiled[0]]->plane_words >= (int64_t)1 << 16) {
     other.push_back(tiled[0]);
     tiled.clear();
