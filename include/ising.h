@@ -456,7 +456,7 @@ typedef struct {
     int32_t status;       /* ISING_OK when done, ISING_AGAIN while running */
     int64_t E_final, M_final;
     uint64_t sweeps_done;
-    double sum_M2, sum_M4; /* exact integer sums over kept sweeps, rounded to double */
+    double sum_M2, sum_M4; /* exact integer sums over kept sweeps, each rounded once to double */
     int64_t n_kept;
     double t_arrive, t_admit, t_done; /* seconds on the host monotonic clock */
 } ising_result;
@@ -494,6 +494,19 @@ ISING_API ising_status ising_server_inject_fault(ising_server_t *s, int64_t quan
 ISING_API ising_status ising_server_stats(const ising_server_t *s, int64_t out[6]);
 
 ISING_API ising_status ising_server_destroy(ising_server_t *s);
+
+/*
+ * The moments a served request reports, for any host series: sum_M2 and
+ * sum_M4 are the exact integer sums of M^2 and M^4 over sweeps
+ * discard .. n - 1 of `series` (n x 2 int64, interleaved E, M, host
+ * memory), each rounded once to the nearest double (M^4 is summed in 256
+ * bits); n_kept = max(n - discard, 0).  These feed the Binder cumulant
+ * U4 = 1 - <M^4> / (3 <M^2>^2) of Eq. (2).  Host only, no device call.
+ * EINVAL for NULL outputs, n < 0, discard < 0, or |M| > 2^42 (no lattice
+ * has more sites).
+ */
+ISING_API ising_status ising_series_moments(const int64_t *series, int64_t n, int64_t discard,
+                                            double *sum_M2, double *sum_M4, int64_t *n_kept);
 
 #ifdef __cplusplus
 }

@@ -154,20 +154,68 @@ ising_status admit(ising_server* s) {
   return ISING_OK;
 }
 
-// Exact sums of M^2 and M^4 over the kept sweeps, rounded once to double.
-void moments(const int64_t* series, int64_t n, int64_t discard, ising_result* r) {
-  unsigned __int128 s2 = 0, s4 = 0;
-  int64_t kept = 0;
-  for (int64_t k = std::max<int64_t>(discard, 0); k < n; ++k) {
-    const __int128 m = series[2 * k + 1];
-    const unsigned __int128 m2 = (unsigned __int128)(m * m);
-    s2 += m2;
-    s4 += m2 * m2;
-    ++kept;
+}  // namespace
+
+// 256-bit unsigned accumulator for sums of M^4: |M| <= L^2 <= 2^42, so one
+// term is below 2^168 and 2^32 of them below 2^200.
+struct U256 {
+  unsigned __int128 lo = 0, hi = 0;
+  void add_square(unsigned __int128 q) {  // += q * q for q < 2^85
+    const uint64_t b = (uint64_t)q;
+    const unsigned __int128 a = q >> 64;  // < 2^21
+    const unsigned __int128 bb = (unsigned __int128)b * b;
+    const unsigned __int128 cross = 2 * a * b;  // < 2^86
+    unsigned __int128 carry = 0;
+    unsigned __int128 t = lo + bb;
+    carry += t < lo;
+    const unsigned __int128 u = t + (cross << 64);
+    carry += u < t;
+    lo = u;
+    hi += a * a + (cross >> 64) + carry;
   }
-  r->sum_M2 = (double)s2;
-  r->sum_M4 = (double)s4;
-  r->n_kept = kept;
+  // Rounded once to the nearest double: the bits below the top 128 only
+  // matter as a sticky bit, which is folded into bit 0 of the shifted value.
+  double to_double() const {
+    if (hi == 0) return (double)lo;
+    int s = 0;
+    for (unsigned __int128 h = hi; h != 0; h >>= 1) ++s;  // bit length of hi, 1..128
+    unsigned __int128 top;
+    bool sticky;
+    if (s == 128) {
+      top = hi;
+      sticky = lo != 0;
+    } else {
+      top = (hi << (128 - s)) | (lo >> s);
+      sticky = (lo & ((((unsigned __int128)1) << s) - 1)) != 0;
+    }
+    return std::ldexp((double)(top | (unsigned __int128)sticky), s);
+  }
+};
+
+// Exact sums of M^2 and M^4 over sweeps discard .. n - 1 of an interleaved
+// (E, M) series, each rounded once to double.
+void exact_moments(const int64_t* series, int64_t n, int64_t discard, double* sum_M2,
+                   double* sum_M4, int64_t* kept) {
+  unsigned __int128 s2 = 0;  // < 2^84 per term, 2^32 terms
+  U256 s4;
+  int64_t k0 = std::max<int64_t>(discard, 0), cnt = 0;
+  for (int64_t k = k0; k < n; ++k) {
+    const int64_t m = series[2 * k + 1];
+    const unsigned __int128 am = (unsigned __int128)(m < 0 ? -(__int128)m : (__int128)m);
+    const unsigned __int128 m2 = am * am;
+    s2 += m2;
+    s4.add_square(m2);
+    ++cnt;
+  }
+  *sum_M2 = (double)s2;
+  *sum_M4 = s4.to_double();
+  *kept = cnt;
+}
+
+namespace {
+
+void moments(const int64_t* series, int64_t n, int64_t discard, ising_result* r) {
+  exact_moments(series, n, discard, &r->sum_M2, &r->sum_M4, &r->n_kept);
 }
 
 ising_status retire(ising_server* s, Job& j) {
@@ -240,6 +288,9 @@ ising_status step(ising_server* s) {
                                     hipMemcpyHostToDevice, s->stream);
       if (e != hipSuccess) return hip_fail(e, "server: restore");
     }
+    // the restore reads host memory that ends with this block
+    hipError_t e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return hip_fail(e, "server: restore");
     s->faults.erase(q);
     ++s->recovered;
   }
@@ -344,6 +395,20 @@ ising_status ising_poll(ising_server_t* s, uint64_t ticket, ising_result* out) {
     return ISING_AGAIN;
   }
   s->jobs.erase(it);
+  return ISING_OK;
+}
+
+ising_status ising_series_moments(const int64_t* series, int64_t n, int64_t discard,
+                                  double* sum_M2, double* sum_M4, int64_t* n_kept) {
+  clear_error();
+  if ((n > 0 && !series) || n < 0 || discard < 0 || !sum_M2 || !sum_M4 || !n_kept)
+    return fail(ISING_EINVAL, "ising_series_moments: bad arguments");
+  for (int64_t k = 0; k < n; ++k) {
+    const int64_t m = series[2 * k + 1];
+    if (m > ((int64_t)1 << 42) || m < -((int64_t)1 << 42))
+      return fail(ISING_EINVAL, "ising_series_moments: |M| > 2^42 at sweep %lld", (long long)k);
+  }
+  exact_moments(series, n, discard, sum_M2, sum_M4, n_kept);
   return ISING_OK;
 }
 

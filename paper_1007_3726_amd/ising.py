@@ -111,6 +111,8 @@ def lib():
         "ising_server_inject_fault": ([vp, i64], i32),
         "ising_server_stats": ([vp, P(i64)], i32),
         "ising_server_destroy": ([vp], i32),
+        "ising_series_moments": ([vp, i64, i64, P(ctypes.c_double), P(ctypes.c_double), P(i64)],
+                                 i32),
         "ising_lcg_bytes": ([i64], ctypes.c_size_t),
         "ising_pool_bytes": ([i32], ctypes.c_size_t),
         "ising_debug_perturb": ([u32], i32),
@@ -673,6 +675,18 @@ def binder_curves(EMs, Ls, temps, discard: int, T_grid, nblocks: int = 20, strea
     K = len(T_grid)
     return {L: (est[j * K:(j + 1) * K], err[j * K:(j + 1) * K], rep[j * K:(j + 1) * K].T.copy())
             for j, L in enumerate(sizes)}
+
+
+def series_moments(series, discard: int = 0):
+    """(sum_M2, sum_M4, n_kept) of an (n, 2) int64 (E, M) series over sweeps
+    discard .. n - 1: exact integer sums, each rounded once to double
+    (ising_series_moments; host only)."""
+    import numpy as np
+    a = np.ascontiguousarray(np.asarray(series, dtype=np.int64).reshape(-1, 2))
+    m2, m4, kept = ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
+    check(lib().ising_series_moments(a.ctypes.data if a.size else None, a.shape[0], int(discard),
+                                     ctypes.byref(m2), ctypes.byref(m4), ctypes.byref(kept)))
+    return m2.value, m4.value, kept.value
 
 
 class Server:
