@@ -119,3 +119,71 @@ def test_missing_library_fails_loudly():
             "    print('raised:', e)\n" % ROOT)
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
     assert "raised:" in r.stdout and "no fallback" in r.stdout, r.stdout + r.stderr
+
+
+def test_rng_state_sizes(L):
+    from paper_1007_3726_amd import ising
+    for m in (10, 16, 22, 28):
+        assert ising.ising_pool_bytes(m) == 16 << m
+    for bad in (-1, 0, 9, 29, 64):
+        assert ising.ising_pool_bytes(bad) == 0
+    # one uint32 state per 64-site word of each colour plane
+    assert ising.ising_lcg_bytes(4) == 2 * 4 * 1 * 4
+    assert ising.ising_lcg_bytes(16384) == 2 * 16384 * 128 * 4
+    assert ising.ising_lcg_bytes(130) == 2 * 130 * 2 * 4
+    for bad in (-2, 0, 2, 5, 2 ** 21 + 2):
+        assert ising.ising_lcg_bytes(bad) == 0
+    assert L.ising_set_rng(None, 0, None, 0) == -1
+
+
+def test_strip_validation_before_device_work(L):
+    part = 2 * 2048 * 8
+    assert L.ising_strip_bytes(128, 1) == 2 * 3 * 1 * 8 + part
+    assert L.ising_strip_bytes(262144, 32768) == 2 * 32770 * 2048 * 8 + part
+    for Lb, rows in ((130, 1), (64, 1), (128, 0), (128, 129), (2 ** 21, 2 ** 21), (2 ** 22, 1)):
+        assert L.ising_strip_bytes(Lb, rows) == 0, (Lb, rows)
+    h = ctypes.c_void_p()
+    buf = ctypes.c_void_p(4096)  # never dereferenced: validation fails first
+    need = L.ising_strip_bytes(256, 64)
+    args = dict(L=256, y0=0, rows=64, seed=1, sid=0, init=2, buf=buf, nbytes=need)
+
+    def create(**kw):
+        a = dict(args, **kw)
+        return L.ising_strip_create(a["L"], a["y0"], a["rows"], a["seed"], a["sid"], a["init"],
+                                    a["buf"], a["nbytes"], None, ctypes.byref(h))
+
+    assert create(L=130) == -1
+    assert create(rows=0) == -1
+    assert create(y0=200) == -1  # rows 200 .. 263 pass the lattice's end
+    assert create(y0=-1) == -1
+    assert create(init=3) == -1
+    assert create(sid=1 << 30) == -1
+    assert create(nbytes=need - 1) == -2
+    assert create(buf=None) == -2
+    assert create(buf=ctypes.c_void_p(4100)) == -1  # not 8-byte aligned
+    assert L.ising_strip_create(256, 0, 64, 1, 0, 2, buf, need, None, None) == -1
+    assert L.ising_strip_set_beta(None, 1.0) == -1
+    assert L.ising_strip_step(None, 0, 0, None) == -1
+    assert L.ising_strip_exchange(None, 1, 0) == -1
+    assert L.ising_strip_get_rows(None, None) == -1
+    assert L.ising_strip_destroy(None) == 0
+    ptr, nb = ctypes.c_void_p(), ctypes.c_size_t()
+    assert L.ising_strip_row(None, 0, 0, ctypes.byref(ptr), ctypes.byref(nb)) == -1
+    assert L.ising_strip_combine(None, 1, 1, 256, None, None) == -1
+    assert L.ising_strip_combine(ctypes.c_void_p(4096), 1, 0, 256, ctypes.c_void_p(4096),
+                                 None) == 0  # nothing to combine: no device work
+
+
+def test_server_validation_before_device_work(L):
+    s = ctypes.c_void_p()
+    arena = ctypes.c_void_p(1 << 20)  # never dereferenced
+    assert L.ising_server_create(arena, 1 << 20, None, 4, None) == -1
+    assert L.ising_server_create(None, 1 << 20, None, 4, ctypes.byref(s)) == -1
+    assert L.ising_server_create(ctypes.c_void_p((1 << 20) + 8), 1 << 20, None, 4,
+                                 ctypes.byref(s)) == -1  # not 256-byte aligned
+    assert L.ising_server_create(arena, 1 << 20, None, 0, ctypes.byref(s)) == -1
+    assert L.ising_server_step(None) == -1
+    assert L.ising_batch_submit(None, None, 0, None) == -1
+    assert L.ising_poll(None, 1, None) == -1
+    assert L.ising_server_inject_fault(None, 0) == -1
+    assert L.ising_server_destroy(None) == 0
