@@ -40,12 +40,15 @@ def main():
         if t in checkpoints:
             digests.append((t, hashlib.sha256(np.ascontiguousarray(s).tobytes()).hexdigest()))
         print("sweep %d done, %.0f s" % (t, time.time() - t0), flush=True)
+    origin = "# written by tests/golden/make_large_plain.py from the oracle alone\n"
     with open(os.path.join(HERE, "large_plain_em.txt"), "w") as f:
+        f.write(origin)
         f.write("# oracle E M after each sweep: L=%d T=%r init=%d seed=%d stream_id=%d\n"
                 % (w.L, w.T, w.init, w.seed, w.stream_id))
         for a, b in em:
             f.write("%d %d\n" % (a, b))
     with open(os.path.join(HERE, "large_plain_sha256.txt"), "w") as f:
+        f.write(origin)
         f.write("# sha256 of the int8 spin array (row-major, +1/-1) after the given sweep\n")
         for t, d in digests:
             f.write("%d %s\n" % (t, d))
