@@ -187,3 +187,35 @@ def test_server_validation_before_device_work(L):
     assert L.ising_poll(None, 1, None) == -1
     assert L.ising_server_inject_fault(None, 0) == -1
     assert L.ising_server_destroy(None) == 0
+
+
+def test_batch_and_reweight_validation_before_device_work(L):
+    assert L.ising_multi_sweep(None, 1, 1, None) == -1
+    two = (ctypes.c_void_p * 2)(None, None)
+    assert L.ising_multi_sweep(two, 2, 1, None) == -1  # NULL handles
+    assert L.ising_multi_sweep(two, -1, 1, None) == -1
+    assert L.ising_multi_sweep_form(None, 1, 1, None, 0, -1) == -1
+    i64 = ctypes.c_int64
+    f64 = ctypes.c_double
+    em = (ctypes.c_void_p * 1)(4096)  # never dereferenced
+    nsw, disc, b0 = (i64 * 1)(100), (i64 * 1)(20), (f64 * 1)(0.44)
+    tl, tb = (ctypes.c_int32 * 1)(0), (f64 * 1)(0.45)
+    sums = ctypes.c_void_p(8192)
+
+    def rw(nlat=1, em=em, nsw=nsw, disc=disc, b0=b0, ntask=1, tl=tl, tb=tb, nblocks=20,
+           sums=sums):
+        return L.ising_reweight(nlat, em, nsw, disc, b0, ntask, tl, tb, nblocks, sums, None,
+                                None)
+
+    assert rw(nlat=0) == -1
+    assert rw(ntask=0) == -1
+    assert rw(em=None) == -1
+    assert rw(sums=None) == -1
+    assert rw(nblocks=0) == -1
+    assert rw(nblocks=1 << 20) == -1
+    assert rw(disc=(i64 * 1)(-1)) == -1
+    assert rw(disc=(i64 * 1)(90)) == -1  # 10 kept sweeps < 20 blocks
+    assert rw(b0=(f64 * 1)(float("nan"))) == -1
+    assert rw(b0=(f64 * 1)(-0.1)) == -1
+    assert rw(tl=(ctypes.c_int32 * 1)(1)) == -1  # no series 1
+    assert rw(tb=(f64 * 1)(float("inf"))) == -1
