@@ -59,6 +59,8 @@ def lib():
         L.oracle_pool_address.restype = u32
         L.oracle_pool_sweeps.argtypes = [i64, u32, u32, u64, u32, u32, i64, i32, i32, p8, p64]
         L.oracle_pool_sweeps.restype = i32
+        L.oracle_band_em.argtypes = [i64, u32, u32, u64, u32, i32, u32, i64, i64, i64, p64]
+        L.oracle_band_em.restype = i32
         L.oracle_get_threads.argtypes = []
         L.oracle_get_threads.restype = i32
         L.oracle_set_threads.argtypes = [i32]
@@ -143,6 +145,32 @@ def window(L, beta, seed, stream_id, init_kind, t0, n, x0, y0, w, h) -> np.ndarr
     if rc != 0:
         raise ValueError("window plus light-cone margin does not fit in the lattice")
     return out
+
+
+def band_em(L, beta, seed, stream_id, init_kind, t0, n, y0, h) -> np.ndarray:
+    """The rows [y0, y0 + h)'s shares of (E, M) after each of n sweeps from a
+    fresh init (light cone over full rows): int64 array [n, 2]."""
+    t4, t8 = thresholds(beta)
+    EM = np.zeros((n, 2), dtype=np.int64)
+    rc = lib().oracle_band_em(L, t4, t8, seed, stream_id, init_kind, t0, n, y0, h, _p64(EM))
+    if rc != 0:
+        raise ValueError("band plus light-cone margin does not fit in the lattice")
+    return EM
+
+
+def lattice_em_by_bands(L, beta, seed, stream_id, init_kind, n, band_rows, progress=None):
+    """Whole-lattice (E, M) after each of n sweeps from a fresh init, summed
+    over bands of at most band_rows rows (memory ~ (band_rows + 4n + 2) L
+    bytes instead of L^2): int64 array [n, 2]."""
+    total = np.zeros((n, 2), dtype=np.int64)
+    y0 = 0
+    while y0 < L:
+        h = min(band_rows, L - y0)
+        total += band_em(L, beta, seed, stream_id, init_kind, 0, n, y0, h)
+        y0 += h
+        if progress is not None:
+            progress(y0)
+    return total
 
 
 def lcg_thresholds(beta: float):

@@ -491,6 +491,85 @@ int oracle_window(int64_t L, uint32_t t4, uint32_t t8, uint64_t seed, uint32_t s
     return 0;
 }
 
+/* ------------------------------------------------------------------ */
+/* Band of rows: energy and magnetisation contributions of the rows    */
+/* [y0, y0 + h) (periodic in L) after each of n sweeps from a fresh     */
+/* start, without holding the whole lattice.  It is the light-cone      */
+/* argument of oracle_window applied to full rows: the band is          */
+/* simulated with m = 2n + 1 extra rows above and below (x is periodic  */
+/* over the full width, so no column margin is needed), the outermost   */
+/* row at each end stays frozen, and after sweep k (k = 1 .. n) rows   */
+/* more than 2k rows from a frozen row equal the full-lattice result.   */
+/* The inner rows and the row just below them are such rows for every  */
+/* k <= n.  EM[2(k-1)] receives the band's share of Eq. (1),            */
+/*   -sum_{y in band} sum_x s(x,y) [s(x+1,y) + s(x,y+1)],               */
+/* (each bond counted at its left or upper end, as oracle_measure       */
+/* does), and EM[2(k-1)+1] the band's sum of spins.  Bands that         */
+/* partition the rows of the lattice therefore sum to the (E, M) of     */
+/* oracle_measure.  Requires h + 2m <= L.  Returns 0, or -1 on a size    */
+/* or allocation error.                                                 */
+/* ------------------------------------------------------------------ */
+int oracle_band_em(int64_t L, uint32_t t4, uint32_t t8, uint64_t seed, uint32_t stream_id,
+                   int init, uint32_t t0, int64_t n, int64_t y0, int64_t h, int64_t *EM)
+{
+    int64_t m = 2 * n + 1;
+    int64_t ph = h + 2 * m;
+    if (ph > L || h <= 0 || n < 0 || L < 4 || (L & 1))
+        return -1;
+    int8_t *p = (int8_t *)malloc((size_t)(ph * L));
+    if (!p)
+        return -1;
+    /* initial state of the patch rows, at global coordinates */
+#pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < ph; ++j) {
+        int64_t gy = wrap(y0 - m + j, L);
+        for (int64_t x = 0; x < L; ++x) {
+            int8_t v;
+            if (init == 0)
+                v = 1;
+            else if (init == 1)
+                v = -1;
+            else {
+                uint32_t colour = (uint32_t)((x + gy) & 1);
+                uint32_t u = oracle_uniform(seed, stream_id, 2u + colour, 0u, L, x, gy);
+                v = (u < 0x80000000u) ? 1 : -1;
+            }
+            p[j * L + x] = v;
+        }
+    }
+    for (int64_t k = 0; k < n; ++k) {
+        uint32_t t = t0 + (uint32_t)k;
+        for (int colour = 0; colour < 2; ++colour) {
+#pragma omp parallel for schedule(static)
+            for (int64_t j = 1; j < ph - 1; ++j) {
+                int64_t gy = wrap(y0 - m + j, L);
+                for (int64_t x = (gy + colour) & 1; x < L; x += 2) {
+                    int v = p[j * L + x];
+                    int n1 = p[j * L + wrap(x - 1, L)];
+                    int n2 = p[j * L + wrap(x + 1, L)];
+                    int n3 = p[(j - 1) * L + x];
+                    int n4 = p[(j + 1) * L + x];
+                    uint32_t u = oracle_uniform(seed, stream_id, (uint32_t)colour, t, L, x, gy);
+                    if (oracle_accept(v, n1, n2, n3, n4, u, t4, t8))
+                        p[j * L + x] = (int8_t)(-v);
+                }
+            }
+        }
+        int64_t e = 0, s = 0;
+#pragma omp parallel for schedule(static) reduction(+ : e, s)
+        for (int64_t j = m; j < m + h; ++j)
+            for (int64_t x = 0; x < L; ++x) {
+                int64_t v = p[j * L + x];
+                e -= v * (p[j * L + wrap(x + 1, L)] + p[(j + 1) * L + x]);
+                s += v;
+            }
+        EM[2 * k] = e;
+        EM[2 * k + 1] = s;
+    }
+    free(p);
+    return 0;
+}
+
 /* Number of OpenMP threads the oracle uses (1 when built without it). */
 int oracle_get_threads(void)
 {
