@@ -143,16 +143,30 @@ ISING_API ising_status ising_set_sweep(ising_t *h, uint64_t t);
 ISING_API ising_status ising_get_info(const ising_t *h, int64_t *L, int64_t *words_per_row, void **planes);
 
 /*
+ * Device bytes of the work buffer ising_multi_sweep needs for these handles
+ * (same conditions on the handles as there; 0 when every lattice takes the
+ * plain path).  The bytes depend only on the lattice sides.  Host only.
+ */
+ISING_API ising_status ising_multi_sweep_work_bytes(ising_t *const *hs, int32_t count,
+                                                    size_t *bytes);
+
+/*
  * Batched sweeps: n sweeps on each of the `count` handles (all created on
  * the same device and stream, each with a beta set, no handle twice),
  * equivalent bit for bit to calling ising_sweep(hs[i], n, dev_EM[i]) on
- * each.  All lattices advance together in fused launches (or, for batches
- * of small lattices, one persistent launch); see ising_multi_sweep_form.
- * dev_EM may be NULL or hold NULL entries.  Each handle's counter advances
- * by n.  Synchronises the stream.  Errors: EINVAL, ERANGE, EDEVICE.
+ * each (section 3's checkerboard sweep, Eqs. (1), (3)-(5), per lattice).
+ * All lattices advance together in fused launches (or, for batches of small
+ * lattices, one persistent launch); see ising_multi_sweep_form.  dev_EM may
+ * be NULL or hold NULL entries.  The task tables go to dev_work (device,
+ * caller-owned, 256-byte aligned, at least ising_multi_sweep_work_bytes
+ * bytes; may be NULL when that is 0); the library allocates no device
+ * memory.  Each handle's counter advances by n.  Synchronises the stream,
+ * so dev_work is free again on return.  Errors: EINVAL, ERANGE, EDEVICE,
+ * ENOMEM (work buffer missing, misaligned or too small).
  */
 ISING_API ising_status ising_multi_sweep(ising_t *const *hs, int32_t count, int64_t n,
-                               int64_t *const *dev_EM);
+                                         int64_t *const *dev_EM, void *dev_work,
+                                         size_t work_bytes);
 
 /*
  * Same as ising_multi_sweep with the launch form chosen by the caller:
@@ -165,7 +179,8 @@ ISING_API ising_status ising_multi_sweep(ising_t *const *hs, int32_t count, int6
  */
 ISING_API ising_status ising_multi_sweep_form(ising_t *const *hs, int32_t count, int64_t n,
                                               int64_t *const *dev_EM, int32_t form,
-                                              int32_t graph_chunk);
+                                              int32_t graph_chunk, void *dev_work,
+                                              size_t work_bytes);
 
 /*
  * Launch form the batched path would choose for lattices of sides Ls[i]
@@ -393,17 +408,26 @@ ISING_API ising_status ising_debug_perturb(uint32_t seed);
  * and w_t = exp(x_t - max x), it writes for every block b the five fp64
  * sums  w, w|M|, w M^2, w M^4, w E  to dev_sums[(k * nblocks + b) * 5 + i]
  * (device, ntask * nblocks * 5 doubles, caller-owned) and max x to
- * dev_shift[k] (device, may be NULL).  1 <= nblocks <= 4096.  The host
- * arrays are read before the call returns; the library copies them to a
- * device table it owns and waits for the stream before the launch; the
- * kernel runs asynchronously on hip_stream.
+ * dev_shift[k] (device, may be NULL).  1 <= nblocks <= 4096.  The task
+ * tables go to dev_work (device, caller-owned, 256-byte aligned, at least
+ * ising_reweight_work_bytes(nlat, ntask) bytes).  The host arrays are read
+ * before the call returns: they are copied to dev_work on hip_stream, the
+ * call waits for that copy, and the kernel then runs asynchronously on
+ * hip_stream, reading dev_work; the caller must not reuse dev_work (or
+ * free it) until the stream has passed the kernel.  Calls on different
+ * streams with different work buffers are independent.  Errors: EINVAL,
+ * ENOMEM (work buffer missing, misaligned or too small), EDEVICE.
  */
 ISING_API ising_status ising_reweight(int32_t nlat, const int64_t *const *dev_EM,
                                       const int64_t *n_sweeps, const int64_t *discard,
                                       const double *beta0, int32_t ntask,
                                       const int32_t *task_lattice, const double *task_beta,
                                       int32_t nblocks, double *dev_sums, double *dev_shift,
-                                      void *hip_stream);
+                                      void *dev_work, size_t work_bytes, void *hip_stream);
+
+/* Device bytes of ising_reweight's work buffer for nlat series and ntask
+ * tasks (0 if either is < 1).  Host only. */
+ISING_API size_t ising_reweight_work_bytes(int32_t nlat, int32_t ntask);
 
 /*
  * From the per-block sums of ising_reweight (host copy, ntask * nblocks * 5
@@ -463,11 +487,15 @@ typedef struct {
 
 /*
  * A server owns nothing on the device except what it carves from the
- * caller's arena (dev_arena, arena_bytes = the HBM budget).  Requests are
- * admitted in FIFO order whenever their lattice fits in the free arena;
- * every quantum runs quantum_sweeps sweeps on all admitted lattices in one
- * fused launch (continuous batching).  Results do not depend on the mix:
+ * caller's arena (dev_arena, 256-byte aligned, arena_bytes = the HBM
+ * budget, caller-owned until ising_server_destroy).  The last 1/32 of the
+ * arena (at least 4 KiB) holds the batched task tables; the rest holds the
+ * lattices and their per-sweep series.  Requests are admitted in FIFO order
+ * whenever their lattice, series and share of the table region fit;
+ * every quantum runs quantum_sweeps sweeps on all admitted lattices in
+ * fused launches (continuous batching).  Results do not depend on the mix:
  * each lattice's uniforms are keyed by its own (seed, stream_id, sweep).
+ * Errors: EINVAL (NULL or misaligned arena, arena under 8 KiB, quantum < 1).
  */
 ISING_API ising_status ising_server_create(void *dev_arena, size_t arena_bytes, void *hip_stream,
                                  int32_t quantum_sweeps, ising_server_t **out);

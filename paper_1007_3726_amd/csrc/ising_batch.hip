@@ -12,7 +12,8 @@
 //     n sweeps with block barriers only.
 // Lattices the tiled layout does not cover (L % 8 != 0, or Philox block
 // indices crossing 2^32 inside a row) are advanced with the plain path.
-// The task tables live in a library-owned device buffer per device.
+// The task tables live in a work buffer the caller provides (device
+// memory, batch_work_bytes of it); the library allocates no device memory.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -31,39 +32,63 @@ bool tile_args(const ising_lattice* h, TileArgs* out);
 
 namespace {
 
-struct DeviceTable {
+// Per-device host state: the compute-unit count and a private stream for
+// graph capture (the caller's stream may be the null stream, which cannot
+// be captured).  The mutex serialises captures on that stream.
+struct DeviceState {
   std::mutex m;
-  void* ptr = nullptr;
-  size_t cap = 0;
   int cus = 0;
-  hipStream_t capture = nullptr;  // private stream for graph capture
+  hipStream_t capture = nullptr;
 };
 
-DeviceTable& table_for(int device) {
-  static DeviceTable tables[64];
-  return tables[device & 63];
+DeviceState& state_for(int device) {
+  static DeviceState states[64];
+  return states[device & 63];
 }
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
-ising_status ensure_table(DeviceTable& T, size_t bytes) {
-  if (T.cap >= bytes) return ISING_OK;
-  if (T.ptr) (void)hipFree(T.ptr);
-  T.ptr = nullptr;
-  T.cap = 0;
-  const size_t want = std::max<size_t>(bytes * 2, 1 << 20);
-  hipError_t e = hipMalloc(&T.ptr, want);
-  if (e != hipSuccess) return hip_fail(e, "batched sweeps: table allocation");
-  T.cap = want;
-  return ISING_OK;
+int cu_count(DeviceState& D, int device) {
+  std::lock_guard<std::mutex> lock(D.m);
+  if (D.cus == 0) {
+    hipDeviceProp_t p;
+    if (hipGetDeviceProperties(&p, device) == hipSuccess) D.cus = p.multiProcessorCount;
+  }
+  return D.cus;
 }
 
-int cu_count(DeviceTable& T, int device) {
-  if (T.cus == 0) {
-    hipDeviceProp_t p;
-    if (hipGetDeviceProperties(&p, device) == hipSuccess) T.cus = p.multiProcessorCount;
-  }
-  return T.cus;
+// Byte offsets of the fused form's tables in the work buffer.
+struct FusedLayout {
+  size_t off_k = 0, off_lat = 256, off_tiles = 0, off_part = 0, bytes = 0;
+};
+
+FusedLayout fused_layout(size_t nl, size_t ntiles) {
+  FusedLayout f;
+  f.off_tiles = align_up(f.off_lat + nl * sizeof(FusedLattice), 256);
+  f.off_part = align_up(f.off_tiles + ntiles * sizeof(FusedTile), 256);
+  // per-wave E/M partials: 2 sweep slots x 4 waves x (anti, up) per tile
+  f.bytes = align_up(f.off_part + 2 * 4 * 2 * ntiles * sizeof(uint32_t), 256);
+  return f;
+}
+
+// Byte offsets of the packed form's tables (one item per lattice, at most
+// one workgroup per lattice).
+struct PackedLayout {
+  size_t off_lat = 0, off_items = 0, off_wgs = 0, bytes = 0;
+};
+
+PackedLayout packed_layout(size_t nl, size_t nitems, size_t nwgs) {
+  PackedLayout p;
+  p.off_items = align_up(nl * sizeof(BatchLattice), 256);
+  p.off_wgs = align_up(p.off_items + nitems * sizeof(BatchItem), 256);
+  p.bytes = align_up(p.off_wgs + nwgs * sizeof(BatchWG), 256);
+  return p;
+}
+
+// Tiles of the fused form's flat mapping for one lattice (RPW row groups per wave).
+int64_t fused_tiles(int64_t plane_words, int32_t rpw) {
+  const int64_t per_tile = 256 * (int64_t)rpw;
+  return (plane_words + per_tile - 1) / per_tile;
 }
 
 }  // namespace
@@ -112,8 +137,8 @@ BatchPlan plan_batch(const std::vector<int64_t>& tiles, int cus, const PlanModel
 
 static ising_status run_fused(ising_lattice* const* hs, const std::vector<int>& idx,
                               const std::vector<TileArgs>& targs, int64_t n, const int64_t* nsw,
-                              int64_t* const* dev_EM, const BatchOptions& opt, DeviceTable& T,
-                              int blocks) {
+                              int64_t* const* dev_EM, const BatchOptions& opt, char* work,
+                              size_t work_bytes, int blocks) {
   hipStream_t stream = hs[idx[0]]->stream;
   const int nl = (int)idx.size();
   std::vector<FusedLattice> lat(nl);
@@ -152,51 +177,53 @@ static ising_status run_fused(ising_lattice* const* hs, const std::vector<int>& 
   }
   const int64_t ntiles = (int64_t)tiles.size();
   blocks = (int)std::min<int64_t>(blocks, std::max<int64_t>(ntiles, 1));
-  const size_t off_k = 0;
-  const size_t off_lat = 256;
-  const size_t off_tiles = align_up(off_lat + nl * sizeof(FusedLattice), 256);
-  const size_t off_part = align_up(off_tiles + ntiles * sizeof(FusedTile), 256);
-  // per-wave E/M partials: 2 sweep slots x 4 waves x (anti, up) per tile
-  const size_t bytes = align_up(off_part + 2 * 4 * 2 * (size_t)ntiles * sizeof(uint32_t), 256);
-  ising_status st = ensure_table(T, bytes);
-  if (st != ISING_OK) return st;
-  char* d = (char*)T.ptr;
-  std::vector<char> img(off_part, 0);
-  std::memcpy(img.data() + off_lat, lat.data(), nl * sizeof(FusedLattice));
-  std::memcpy(img.data() + off_tiles, tiles.data(), ntiles * sizeof(FusedTile));
-  hipError_t e = hipMemcpyAsync(d, img.data(), img.size(), hipMemcpyHostToDevice, stream);
+  const FusedLayout fl = fused_layout(nl, ntiles);
+  if (fl.bytes > work_bytes)
+    return fail(ISING_ENOMEM, "batched sweeps: work buffer of %zu bytes < %zu needed", work_bytes,
+                fl.bytes);
+  // the image covers the sweep counter (zero) and the tables; the partials
+  // are written before they are read
+  std::vector<char> img(fl.off_part, 0);
+  std::memcpy(img.data() + fl.off_lat, lat.data(), nl * sizeof(FusedLattice));
+  std::memcpy(img.data() + fl.off_tiles, tiles.data(), ntiles * sizeof(FusedTile));
+  hipError_t e = hipMemcpyAsync(work, img.data(), img.size(), hipMemcpyHostToDevice, stream);
+  if (e != hipSuccess) return hip_fail(e, "batched sweeps: table upload");
+  // the host image ends with this call
+  e = hipStreamSynchronize(stream);
   if (e != hipSuccess) return hip_fail(e, "batched sweeps: table upload");
 
   FusedArgs f;
-  f.lat = (const FusedLattice*)(d + off_lat);
+  f.lat = (const FusedLattice*)(work + fl.off_lat);
   f.nlat = nl;
   f.klocal = 0;
-  f.tiles = (const FusedTile*)(d + off_tiles);
+  f.tiles = (const FusedTile*)(work + fl.off_tiles);
   f.ntiles = ntiles;
-  f.kbase = (const uint32_t*)(d + off_k);
-  f.part = (uint32_t*)(d + off_part);
-  uint32_t* kbase = (uint32_t*)(d + off_k);
+  f.kbase = (const uint32_t*)(work + fl.off_k);
+  f.part = (uint32_t*)(work + fl.off_part);
+  uint32_t* kbase = (uint32_t*)(work + fl.off_k);
 
   int64_t done = 0;
   const int K = opt.graph_chunk;
   if (K > 0 && n >= 2 * (int64_t)K) {
     // capture K sweeps (+ the counter advance) once on a private stream,
     // then replay the chunk n / K times on the caller's stream
-    if (!T.capture) {
-      e = hipStreamCreateWithFlags(&T.capture, hipStreamNonBlocking);
+    DeviceState& D = state_for(hs[idx[0]]->device);
+    std::lock_guard<std::mutex> lock(D.m);
+    if (!D.capture) {
+      e = hipStreamCreateWithFlags(&D.capture, hipStreamNonBlocking);
       if (e != hipSuccess) return hip_fail(e, "batched sweeps: capture stream");
     }
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    e = hipStreamBeginCapture(T.capture, hipStreamCaptureModeThreadLocal);
+    e = hipStreamBeginCapture(D.capture, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
       for (int k = 0; k < K && e == hipSuccess; ++k) {
         f.klocal = k;
-        e = launch_fused(T.capture, 0, f, blocks);
-        if (e == hipSuccess) e = launch_fused(T.capture, 1, f, blocks);
+        e = launch_fused(D.capture, 0, f, blocks);
+        if (e == hipSuccess) e = launch_fused(D.capture, 1, f, blocks);
       }
-      if (e == hipSuccess) e = launch_advance(T.capture, kbase, (uint32_t)K);
-      hipError_t e2 = hipStreamEndCapture(T.capture, &graph);
+      if (e == hipSuccess) e = launch_advance(D.capture, kbase, (uint32_t)K);
+      hipError_t e2 = hipStreamEndCapture(D.capture, &graph);
       if (e == hipSuccess) e = e2;
     }
     if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
@@ -209,15 +236,24 @@ static ising_status run_fused(ising_lattice* const* hs, const std::vector<int>& 
     if (e != hipSuccess) return hip_fail(e, "batched sweeps: graph capture/replay");
     done = reps * K;
   }
-  // remaining sweeps: direct launches at kbase + klocal
+  // remaining sweeps: direct launches at kbase + klocal; the device counter
+  // moves on every 2^20 sweeps so that klocal stays small
+  const int64_t kStep = int64_t(1) << 20;
+  int64_t base = 0;
   for (int64_t k = 0; k < n - done; ++k) {
-    f.klocal = (int32_t)k;
+    if (k - base == kStep) {
+      e = launch_advance(stream, kbase, (uint32_t)kStep);
+      if (e != hipSuccess) return hip_fail(e, "batched sweeps: counter advance");
+      base = k;
+    }
+    f.klocal = (int32_t)(k - base);
     e = launch_fused(stream, 0, f, blocks);
     if (e == hipSuccess) e = launch_fused(stream, 1, f, blocks);
     if (e != hipSuccess) return hip_fail(e, "batched sweeps: fused launch");
   }
   if (any_em) {
-    f.klocal = (int32_t)(n - done) - 1;  // the last sweep: kbase + klocal = n - 1
+    // the last sweep: kbase + klocal = n - 1
+    f.klocal = n - done > 0 ? (int32_t)(n - done - 1 - base) : -1;
     e = launch_fused_finalize(stream, f, std::min(nl, 1024));
     if (e != hipSuccess) return hip_fail(e, "batched sweeps: finalize launch");
   }
@@ -228,7 +264,8 @@ static ising_status run_fused(ising_lattice* const* hs, const std::vector<int>& 
 
 static ising_status run_packed(ising_lattice* const* hs, const std::vector<int>& idx,
                                const std::vector<TileArgs>& targs, int64_t n, const int64_t* nsw,
-                               int64_t* const* dev_EM, const BatchPlan& plan, DeviceTable& T) {
+                               int64_t* const* dev_EM, const BatchPlan& plan, char* work,
+                               size_t work_bytes) {
   hipStream_t stream = hs[idx[0]]->stream;
   const int nl = (int)idx.size();
   std::vector<BatchLattice> lat(nl);
@@ -248,38 +285,34 @@ static ising_status run_packed(ising_lattice* const* hs, const std::vector<int>&
     wgs[b].n_items = (int32_t)plan.packs[b].size();
     for (int j : plan.packs[b]) items.push_back(BatchItem{j, 0});
   }
-  const size_t off_lat = 0;
-  const size_t off_items = align_up(nl * sizeof(BatchLattice), 256);
-  const size_t off_wgs = align_up(off_items + items.size() * sizeof(BatchItem), 256);
-  const size_t bytes = align_up(off_wgs + wgs.size() * sizeof(BatchWG), 256);
-  ising_status st = ensure_table(T, bytes);
-  if (st != ISING_OK) return st;
-  std::vector<char> img(bytes, 0);
-  std::memcpy(img.data() + off_lat, lat.data(), nl * sizeof(BatchLattice));
-  std::memcpy(img.data() + off_items, items.data(), items.size() * sizeof(BatchItem));
-  std::memcpy(img.data() + off_wgs, wgs.data(), wgs.size() * sizeof(BatchWG));
-  char* d = (char*)T.ptr;
-  hipError_t e = hipMemcpyAsync(d, img.data(), img.size(), hipMemcpyHostToDevice, stream);
+  const PackedLayout pl = packed_layout(nl, items.size(), wgs.size());
+  if (pl.bytes > work_bytes)
+    return fail(ISING_ENOMEM, "batched sweeps: work buffer of %zu bytes < %zu needed", work_bytes,
+                pl.bytes);
+  std::vector<char> img(pl.bytes, 0);
+  std::memcpy(img.data() + pl.off_lat, lat.data(), nl * sizeof(BatchLattice));
+  std::memcpy(img.data() + pl.off_items, items.data(), items.size() * sizeof(BatchItem));
+  std::memcpy(img.data() + pl.off_wgs, wgs.data(), wgs.size() * sizeof(BatchWG));
+  hipError_t e = hipMemcpyAsync(work, img.data(), img.size(), hipMemcpyHostToDevice, stream);
   if (e != hipSuccess) return hip_fail(e, "batched sweeps: table upload");
   BatchArgs a;
-  a.lat = (const BatchLattice*)(d + off_lat);
-  a.items = (const BatchItem*)(d + off_items);
-  a.wgs = (const BatchWG*)(d + off_wgs);
+  a.lat = (const BatchLattice*)(work + pl.off_lat);
+  a.items = (const BatchItem*)(work + pl.off_items);
+  a.wgs = (const BatchWG*)(work + pl.off_wgs);
   a.n = n;
   e = launch_batch(stream, a, (int)wgs.size());
+  // the host image must outlive the upload: wait before it goes
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
   if (e != hipSuccess) return hip_fail(e, "batched sweeps: packed launch");
   return ISING_OK;
 }
 
-ising_status batch_sweeps(ising_lattice* const* hs, int32_t count, int64_t n,
-                          const int64_t* nsw, int64_t* const* dev_EM, const BatchOptions& opt,
-                          int* form_out) {
-  if (form_out) *form_out = -1;
-  if (count == 0 || n == 0) return ISING_OK;
-  const int device = hs[0]->device;
-  std::vector<int> tiled, other;
-  std::vector<TileArgs> targs(count);
+// Which lattices take the tiled batched kernels (their tile arguments in
+// targs) and which the plain path.
+static void classify(ising_lattice* const* hs, int32_t count, const BatchOptions& opt,
+                     std::vector<int>& tiled, std::vector<int>& other,
+                     std::vector<TileArgs>& targs) {
+  targs.assign(count, TileArgs{});
   for (int i = 0; i < count; ++i) {
     TileArgs ta;
     // the fused kernel indexes a plane with 32-bit word numbers: planes of
@@ -308,6 +341,49 @@ ising_status batch_sweeps(ising_lattice* const* hs, int32_t count, int64_t n,
     other.push_back(tiled[0]);
     tiled.clear();
   }
+}
+
+// Work-buffer bytes for the tiled lattices: the larger of the two forms.
+static size_t work_bytes_for(ising_lattice* const* hs, const std::vector<int>& tiled,
+                             const std::vector<TileArgs>& targs) {
+  if (tiled.empty()) return 0;
+  size_t ntiles = 0;
+  for (int i : tiled) ntiles += (size_t)fused_tiles(hs[i]->plane_words, targs[i].RPW);
+  const size_t nl = tiled.size();
+  return std::max(fused_layout(nl, ntiles).bytes, packed_layout(nl, nl, nl).bytes);
+}
+
+size_t batch_work_bytes(ising_lattice* const* hs, int32_t count, const BatchOptions& opt) {
+  std::vector<int> tiled, other;
+  std::vector<TileArgs> targs;
+  classify(hs, count, opt, tiled, other, targs);
+  return work_bytes_for(hs, tiled, targs);
+}
+
+size_t batch_work_share(int64_t L) {
+  const int64_t plane_words = L * words_per_row(L);
+  const size_t fused = sizeof(FusedLattice) +
+                       (size_t)fused_tiles(plane_words, 1) * (sizeof(FusedTile) + 64);
+  const size_t packed = sizeof(BatchLattice) + sizeof(BatchItem) + sizeof(BatchWG);
+  return std::max(fused, packed);
+}
+
+ising_status batch_sweeps(ising_lattice* const* hs, int32_t count, int64_t n,
+                          const int64_t* nsw, int64_t* const* dev_EM, const BatchOptions& opt,
+                          void* work, size_t work_bytes, int* form_out) {
+  if (form_out) *form_out = -1;
+  if (count == 0 || n == 0) return ISING_OK;
+  const int device = hs[0]->device;
+  std::vector<int> tiled, other;
+  std::vector<TileArgs> targs;
+  classify(hs, count, opt, tiled, other, targs);
+  if (!tiled.empty()) {
+    const size_t need = work_bytes_for(hs, tiled, targs);
+    if (!work || need > work_bytes || ((uintptr_t)work & 255))
+      return fail(ISING_ENOMEM,
+                  "batched sweeps: needs a 256-byte aligned work buffer of %zu bytes (got %zu)",
+                  need, work ? work_bytes : (size_t)0);
+  }
   for (int i : other) {
     // the plain path reads the handle's counter: advance a copy of it
     ising_lattice tmp = *hs[i];
@@ -318,9 +394,7 @@ ising_status batch_sweeps(ising_lattice* const* hs, int32_t count, int64_t n,
     hipError_t e = hipStreamSynchronize(hs[0]->stream);
     return e == hipSuccess ? ISING_OK : hip_fail(e, "batched sweeps: synchronize");
   }
-  DeviceTable& T = table_for(device);
-  std::lock_guard<std::mutex> lock(T.m);
-  const int cus = cu_count(T, device);
+  const int cus = cu_count(state_for(device), device);
   if (cus <= 0) return fail(ISING_EDEVICE, "batched sweeps: no device properties");
   std::vector<int64_t> tiles;
   for (int i : tiled) tiles.push_back(tile_cost(targs[i].tiles, targs[i].RPW));
@@ -329,12 +403,12 @@ ising_status batch_sweeps(ising_lattice* const* hs, int32_t count, int64_t n,
   if (opt.force_form == 0) packed = false;
   if (opt.force_form == 1) packed = true;
   if (form_out) *form_out = packed ? 1 : 0;
-  if (packed) return run_packed(hs, tiled, targs, n, nsw, dev_EM, plan, T);
+  if (packed) return run_packed(hs, tiled, targs, n, nsw, dev_EM, plan, (char*)work, work_bytes);
   // the fused grid walks actual tiles; size it for them
   int64_t ntiles = 0;
   for (int i : tiled) ntiles += targs[i].tiles;
   const int blocks = (int)std::min<int64_t>(std::max<int64_t>(ntiles, 1), plan.fused_blocks);
-  return run_fused(hs, tiled, targs, n, nsw, dev_EM, opt, T, blocks);
+  return run_fused(hs, tiled, targs, n, nsw, dev_EM, opt, (char*)work, work_bytes, blocks);
 }
 
 }  // namespace ising
@@ -383,14 +457,27 @@ static ising_status check_batch(ising_t* const* hs, int32_t count, int64_t n, co
   return ISING_OK;
 }
 
+extern "C" ising_status ising_multi_sweep_work_bytes(ising_t* const* hs, int32_t count,
+                                                     size_t* bytes) {
+  clear_error();
+  if (!bytes) return fail(ISING_EINVAL, "ising_multi_sweep_work_bytes: bytes is NULL");
+  *bytes = 0;
+  ising_status st = check_batch(hs, count, 0, "ising_multi_sweep_work_bytes");
+  if (st != ISING_OK) return st;
+  *bytes = batch_work_bytes(hs, count, default_batch_options());
+  return ISING_OK;
+}
+
 extern "C" ising_status ising_multi_sweep(ising_t* const* hs, int32_t count, int64_t n,
-                                          int64_t* const* dev_EM) {
-  return ising_multi_sweep_form(hs, count, n, dev_EM, -1, -1);
+                                          int64_t* const* dev_EM, void* dev_work,
+                                          size_t work_bytes) {
+  return ising_multi_sweep_form(hs, count, n, dev_EM, -1, -1, dev_work, work_bytes);
 }
 
 extern "C" ising_status ising_multi_sweep_form(ising_t* const* hs, int32_t count, int64_t n,
                                                int64_t* const* dev_EM, int32_t form,
-                                               int32_t graph_chunk) {
+                                               int32_t graph_chunk, void* dev_work,
+                                               size_t work_bytes) {
   clear_error();
   ising_status st = check_batch(hs, count, n, "ising_multi_sweep");
   if (st != ISING_OK) return st;
@@ -399,7 +486,7 @@ extern "C" ising_status ising_multi_sweep_form(ising_t* const* hs, int32_t count
   BatchOptions opt = default_batch_options();
   opt.force_form = form;
   if (graph_chunk >= 0) opt.graph_chunk = graph_chunk;
-  st = batch_sweeps(hs, count, n, nullptr, dev_EM, opt, nullptr);
+  st = batch_sweeps(hs, count, n, nullptr, dev_EM, opt, dev_work, work_bytes, nullptr);
   if (st != ISING_OK) return st;
   for (int32_t i = 0; i < count; ++i) hs[i]->sweep += (uint64_t)n;
   return ISING_OK;

@@ -37,10 +37,19 @@ struct BatchOptions {
 PlanModel default_model();
 BatchOptions default_batch_options();
 BatchPlan plan_batch(const std::vector<int64_t>& tiles, int cus, const PlanModel& model);
-// Advance hs[i] by nsw[i] sweeps (nsw may be null: n for all), n = max nsw.
-// Does not change the handles' sweep counters.
+// Device bytes of the work buffer batch_sweeps needs for these handles
+// (0 when every lattice takes the plain path).
+size_t batch_work_bytes(ising_lattice* const* hs, int32_t count, const BatchOptions& opt);
+// An upper bound of one lattice's share of that buffer, whatever the form
+// and the rest of the batch: batch_work_bytes of a set of lattices is at most
+// kBatchWorkFixed plus the sum of their shares.
+size_t batch_work_share(int64_t L);
+constexpr size_t kBatchWorkFixed = 4 * 256;
+// Advance hs[i] by nsw[i] sweeps (nsw may be null: n for all), n = max nsw,
+// with the task tables in `work` (device, 256-byte aligned, work_bytes >=
+// batch_work_bytes).  Does not change the handles' sweep counters.
 ising_status batch_sweeps(ising_lattice* const* hs, int32_t count, int64_t n,
                           const int64_t* nsw, int64_t* const* dev_EM, const BatchOptions& opt,
-                          int* form_out);
+                          void* work, size_t work_bytes, int* form_out);
 
 }  // namespace ising

@@ -24,7 +24,6 @@
 #include <cmath>
 #include <cstring>
 #include <limits>
-#include <mutex>
 #include <vector>
 
 #include "ising.h"
@@ -120,16 +119,11 @@ __global__ __launch_bounds__(kRwThreads) void k_reweight(const RwLattice* lat, c
   if (threadIdx.x == 0 && shift) shift[blockIdx.x] = xm;
 }
 
-// Library-owned device buffer per device for the task tables.
-struct RwTable {
-  std::mutex m;
-  void* ptr = nullptr;
-  size_t cap = 0;
-};
-
-RwTable& rw_table(int device) {
-  static RwTable tables[64];
-  return tables[device & 63];
+// Layout of the task tables in the caller's work buffer: the series
+// table, then (256-byte aligned) the task list.
+size_t rw_task_offset(int32_t nlat) { return ((size_t)nlat * sizeof(RwLattice) + 255) / 256 * 256; }
+size_t rw_work_bytes(int32_t nlat, int32_t ntask) {
+  return rw_task_offset(nlat) + (size_t)ntask * sizeof(RwTask);
 }
 
 bool finite_nonneg(double v) { return std::isfinite(v) && v >= 0.0; }
@@ -165,15 +159,24 @@ using namespace ising;
 
 extern "C" {
 
+size_t ising_reweight_work_bytes(int32_t nlat, int32_t ntask) {
+  if (nlat < 1 || ntask < 1) return 0;
+  return rw_work_bytes(nlat, ntask);
+}
+
 ising_status ising_reweight(int32_t nlat, const int64_t* const* dev_EM, const int64_t* n_sweeps,
                             const int64_t* discard, const double* beta0, int32_t ntask,
                             const int32_t* task_lattice, const double* task_beta,
                             int32_t nblocks, double* dev_sums, double* dev_shift,
-                            void* hip_stream) {
+                            void* dev_work, size_t work_bytes, void* hip_stream) {
   clear_error();
   if (nlat < 1 || ntask < 1 || !dev_EM || !n_sweeps || !discard || !beta0 || !task_lattice ||
       !task_beta || !dev_sums)
     return fail(ISING_EINVAL, "ising_reweight: bad arguments");
+  if (!dev_work || ((uintptr_t)dev_work & 255) || work_bytes < rw_work_bytes(nlat, ntask))
+    return fail(ISING_ENOMEM,
+                "ising_reweight: needs a 256-byte aligned work buffer of %zu bytes (got %zu)",
+                rw_work_bytes(nlat, ntask), dev_work ? work_bytes : (size_t)0);
   if (nblocks < 1 || nblocks > kRwMaxBlocks)
     return fail(ISING_EINVAL, "ising_reweight: nblocks must be in 1..%d", kRwMaxBlocks);
   std::vector<RwLattice> lat((size_t)nlat);
@@ -192,33 +195,19 @@ ising_status ising_reweight(int32_t nlat, const int64_t* const* dev_EM, const in
       return fail(ISING_EINVAL, "ising_reweight: task %d has a bad series index or beta", k);
     tasks[k] = RwTask{task_lattice[k], 0, task_beta[k]};
   }
-  int device = 0;
-  hipError_t e = hipGetDevice(&device);
-  if (e != hipSuccess) return hip_fail(e, "ising_reweight: device");
-  RwTable& T = rw_table(device);
-  std::lock_guard<std::mutex> lock(T.m);
-  const size_t off_task = (nlat * sizeof(RwLattice) + 255) / 256 * 256;
-  const size_t bytes = off_task + ntask * sizeof(RwTask);
-  if (T.cap < bytes) {
-    if (T.ptr) (void)hipFree(T.ptr);
-    T.ptr = nullptr;
-    T.cap = 0;
-    const size_t want = bytes * 2 > (64u << 10) ? bytes * 2 : (64u << 10);
-    e = hipMalloc(&T.ptr, want);
-    if (e != hipSuccess) return hip_fail(e, "ising_reweight: table allocation");
-    T.cap = want;
-  }
+  const size_t off_task = rw_task_offset(nlat);
+  const size_t bytes = rw_work_bytes(nlat, ntask);
   std::vector<char> img(bytes, 0);
   std::memcpy(img.data(), lat.data(), nlat * sizeof(RwLattice));
   std::memcpy(img.data() + off_task, tasks.data(), ntask * sizeof(RwTask));
   const hipStream_t st = (hipStream_t)hip_stream;
-  e = hipMemcpyAsync(T.ptr, img.data(), bytes, hipMemcpyHostToDevice, st);
+  hipError_t e = hipMemcpyAsync(dev_work, img.data(), bytes, hipMemcpyHostToDevice, st);
   if (e != hipSuccess) return hip_fail(e, "ising_reweight: table upload");
   // the host image must outlive the copy
   e = hipStreamSynchronize(st);
   if (e != hipSuccess) return hip_fail(e, "ising_reweight: table upload");
-  hipLaunchKernelGGL(k_reweight, dim3(ntask), dim3(kRwThreads), 0, st, (const RwLattice*)T.ptr,
-                     (const RwTask*)((char*)T.ptr + off_task), nblocks, dev_sums, dev_shift);
+  hipLaunchKernelGGL(k_reweight, dim3(ntask), dim3(kRwThreads), 0, st, (const RwLattice*)dev_work,
+                     (const RwTask*)((char*)dev_work + off_task), nblocks, dev_sums, dev_shift);
   e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "ising_reweight: launch");
   return ISING_OK;

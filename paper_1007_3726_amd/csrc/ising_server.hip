@@ -8,7 +8,10 @@
 //      whole arena is rejected at submission;
 //   2. one batched call advances every active lattice by up to
 //      quantum_sweeps sweeps (fewer for a request that has fewer left), all
-//      lattices together in fused launches or one packed launch;
+//      lattices together in fused launches or one packed launch, with the
+//      task tables in a region reserved at the end of the arena (1/32 of
+//      it; every admitted lattice also reserves its share of that region,
+//      so the tables of any active set fit);
 //   3. retirement: finished requests copy their series/spins to the
 //      caller's host buffers, get exact moment sums, a completion time, and
 //      free their arena space, so the next step can admit more.
@@ -93,6 +96,7 @@ struct Job {
   ising_request req;
   State state = State::Queued;
   size_t off = 0, bytes = 0;   // arena slice: lattice then series
+  size_t share = 0;            // reserved bytes of the task-table region
   ising_lattice* h = nullptr;
   int64_t* dev_series = nullptr;
   int64_t done = 0;            // sweeps completed
@@ -110,7 +114,10 @@ using namespace ising;
 
 struct ising_server {
   char* arena_base;
-  size_t arena_bytes;
+  size_t arena_bytes;   // lattice and series space: [0, arena_bytes)
+  char* table;          // task-table region: [arena_bytes, arena_bytes + table_bytes)
+  size_t table_bytes;
+  size_t table_used = kBatchWorkFixed;  // the fixed part plus the active shares
   hipStream_t stream;
   int32_t quantum;
   Arena arena;
@@ -130,7 +137,9 @@ ising_status admit(ising_server* s) {
   while (!s->queue.empty()) {
     Job& j = s->jobs.at(s->queue.front());
     size_t off;
-    if (!s->arena.alloc(j.bytes, &off)) break;  // strict FIFO: wait for space
+    // strict FIFO: wait for space in the arena and in the table region
+    if (s->table_used + j.share > s->table_bytes) break;
+    if (!s->arena.alloc(j.bytes, &off)) break;
     j.off = off;
     ising_t* h = nullptr;
     const size_t lb = align256(lattice_bytes(j.req.L));
@@ -143,6 +152,7 @@ ising_status admit(ising_server* s) {
       return st;
     }
     j.h = h;
+    s->table_used += j.share;
     j.dev_series = (int64_t*)(s->arena_base + off + lb);
     j.state = State::Active;
     j.res.t_admit = now_s();
@@ -239,6 +249,7 @@ ising_status retire(ising_server* s, Job& j) {
   ising_destroy(j.h);
   j.h = nullptr;
   s->arena.release(j.off, j.bytes);
+  s->table_used -= j.share;
   j.state = State::Done;
   ++s->finished;
   return ISING_OK;
@@ -249,7 +260,7 @@ ising_status run_quantum(ising_server* s, std::vector<ising_lattice*>& hs,
                          std::vector<int64_t>& nsw, std::vector<int64_t*>& ems, int64_t n) {
   BatchOptions opt = default_batch_options();
   ising_status st = batch_sweeps(hs.data(), (int32_t)hs.size(), n, nsw.data(), ems.data(), opt,
-                                 nullptr);
+                                 s->table, s->table_bytes, nullptr);
   if (st != ISING_OK) return st;
   hipError_t e = hipStreamSynchronize(s->stream);
   return e == hipSuccess ? ISING_OK : hip_fail(e, "server: quantum");
@@ -326,10 +337,17 @@ ising_status ising_server_create(void* dev_arena, size_t arena_bytes, void* hip_
     return fail(ISING_EINVAL, "ising_server_create: arena must be non-NULL, 256-B aligned");
   if (quantum_sweeps < 1)
     return fail(ISING_EINVAL, "ising_server_create: quantum_sweeps must be >= 1");
-  ising_server* s = new (std::nothrow) ising_server(arena_bytes & ~(size_t)255);
+  // the last 1/32 of the arena (at least 4 KiB) holds the batched task tables
+  const size_t total = arena_bytes & ~(size_t)255;
+  const size_t table = std::max<size_t>((total / 32) & ~(size_t)255, 4096);
+  if (total < 2 * table)
+    return fail(ISING_EINVAL, "ising_server_create: arena of %zu bytes is too small", total);
+  ising_server* s = new (std::nothrow) ising_server(total - table);
   if (!s) return fail(ISING_ENOMEM, "ising_server_create: host allocation failed");
   s->arena_base = (char*)dev_arena;
-  s->arena_bytes = arena_bytes & ~(size_t)255;
+  s->arena_bytes = total - table;
+  s->table = (char*)dev_arena + (total - table);
+  s->table_bytes = table;
   s->stream = (hipStream_t)hip_stream;
   s->quantum = quantum_sweeps;
   *out = s;
@@ -355,7 +373,7 @@ ising_status ising_batch_submit(ising_server_t* s, const ising_request* reqs, in
       return fail(ISING_EINVAL, "ising_batch_submit: request %d: series buffer missing", i);
     if ((r.flags & ISING_REQ_RETURN_SPINS) && !r.spins_out)
       return fail(ISING_EINVAL, "ising_batch_submit: request %d: spins buffer missing", i);
-    if (job_bytes(r) > s->arena_bytes)
+    if (job_bytes(r) > s->arena_bytes || kBatchWorkFixed + batch_work_share(r.L) > s->table_bytes)
       return fail(ISING_ENOMEM, "ising_batch_submit: request %d needs %zu bytes > arena %zu", i,
                   job_bytes(r), s->arena_bytes);
   }
@@ -365,6 +383,7 @@ ising_status ising_batch_submit(ising_server_t* s, const ising_request* reqs, in
     j.ticket = s->next_ticket++;
     j.req = reqs[i];
     j.bytes = job_bytes(reqs[i]);
+    j.share = batch_work_share(reqs[i].L);
     std::memset(&j.res, 0, sizeof(j.res));
     j.res.ticket = j.ticket;
     j.res.status = ISING_AGAIN;

@@ -96,8 +96,10 @@ def lib():
         "ising_get_sweep": ([vp, P(u64)], i32),
         "ising_set_sweep": ([vp, u64], i32),
         "ising_get_info": ([vp, P(i64), P(i64), P(vp)], i32),
-        "ising_multi_sweep": ([P(vp), i32, i64, P(vp)], i32),
-        "ising_multi_sweep_form": ([P(vp), i32, i64, P(vp), i32, i32], i32),
+        "ising_multi_sweep_work_bytes": ([P(vp), i32, P(ctypes.c_size_t)], i32),
+        "ising_multi_sweep": ([P(vp), i32, i64, P(vp), vp, ctypes.c_size_t], i32),
+        "ising_multi_sweep_form": ([P(vp), i32, i64, P(vp), i32, i32, vp, ctypes.c_size_t],
+                                   i32),
         "ising_batch_plan": ([P(i64), i32, i32, P(i32), P(i32), P(ctypes.c_double)], i32),
         "ising_autotune": ([i64, vp, ctypes.c_size_t, vp, i32, P(ising_tuning)], i32),
         "ising_tuning_set": ([P(ising_tuning), i32], i32),
@@ -128,7 +130,8 @@ def lib():
         "ising_strip_combine": ([vp, i32, i64, i64, vp, vp], i32),
         "ising_set_rng": ([vp, i32, vp, ctypes.c_size_t], i32),
         "ising_reweight": ([i32, P(vp), P(i64), P(i64), P(ctypes.c_double), i32, P(i32),
-                            P(ctypes.c_double), i32, vp, vp, vp], i32),
+                            P(ctypes.c_double), i32, vp, vp, vp, ctypes.c_size_t, vp], i32),
+        "ising_reweight_work_bytes": ([i32, i32], ctypes.c_size_t),
         "ising_fss_moments": ([vp, i32, i32, P(i64), vp, vp, vp], i32),
         "ising_binder_crossing": ([vp, i32, vp, vp, vp, vp, i32, vp], i32),
     }
@@ -254,124 +257,6 @@ class StripSet:
             check(lib().ising_strip_get_rows(h, part.ctypes.data))
             out[y0:y0 + r] = part
             y0 += r
-        return out
-
-
-class DistStrip:
-    """This process's strip of an L x L lattice split over the ranks of a
-    torch.distributed group: rank r owns the r-th band of rows (as even as
-    possible).  After every colour step the boundary rows of that colour
-    move to the neighbouring ranks by point-to-point send/recv (the first
-    row up, the last row down; with the nccl backend, i.e. RCCL, straight
-    from device memory, with gloo staged through host memory), and the
-    per-sweep bond and spin counts are summed by one all-reduce.  A group of
-    one rank refreshes its halos from its own rows without any transport.
-    The result equals the whole lattice's bit for bit."""
-
-    def __init__(self, L: int, group=None, seed: int = 1, stream_id: int = 0,
-                 init: int = INIT_HOT, beta: Optional[float] = None, device="cuda"):
-        import torch
-        import torch.distributed as dist
-        self.group = group
-        self.world = dist.get_world_size(group)
-        self.rank = dist.get_rank(group)
-        self.host_staged = dist.get_backend(group) != "nccl"
-        base, extra = divmod(L, self.world)
-        rows = [base + (1 if k < extra else 0) for k in range(self.world)]
-        self.L, self.rows, self.y0 = L, rows[self.rank], sum(rows[:self.rank])
-        self.device = device
-        self.stream = torch.cuda.current_stream(device)
-        nbytes = int(lib().ising_strip_bytes(L, self.rows))
-        if nbytes == 0:
-            raise IsingError(ISING_EINVAL, "unsupported strip shape L=%d rows=%d" % (L, self.rows))
-        self.buf = _dev_alloc(nbytes, device)
-        self.h = ctypes.c_void_p()
-        check(lib().ising_strip_create(L, self.y0, self.rows, seed, stream_id, init,
-                                       self.buf.data_ptr(), nbytes, _stream_ptr(self.stream),
-                                       ctypes.byref(self.h)))
-        self.W = L // 128
-        self.t = 0
-        if beta is not None:
-            check(lib().ising_strip_set_beta(self.h, beta))
-        for c in (0, 1):
-            self._exchange(c)
-
-    def close(self):
-        if self.h:
-            lib().ising_strip_destroy(self.h)
-            self.h = None
-
-    def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass
-
-    def set_beta(self, beta: float):
-        check(lib().ising_strip_set_beta(self.h, beta))
-
-    def _row(self, colour: int, which: int):
-        ptr, nbytes = ctypes.c_void_p(), ctypes.c_size_t()
-        check(lib().ising_strip_row(self.h, colour, which, ctypes.byref(ptr), ctypes.byref(nbytes)))
-        off = ptr.value - self.buf.data_ptr()
-        return self.buf[off:off + nbytes.value]
-
-    def _exchange(self, colour: int):
-        import torch.distributed as dist
-        if self.world == 1:  # both neighbours are this strip: its own rows, no transport
-            check(lib().ising_strip_exchange((ctypes.c_void_p * 1)(self.h.value), 1, colour))
-            return
-        up = (self.rank - 1) % self.world
-        down = (self.rank + 1) % self.world
-        first, last = self._row(colour, 1), self._row(colour, 2)
-        above, below = self._row(colour, 0), self._row(colour, 3)
-        if self.host_staged:
-            first, last = first.cpu(), last.cpu()  # waits for the colour step
-            above_x, below_x = first.new_empty(first.shape), first.new_empty(first.shape)
-        else:
-            above_x, below_x = above, below
-        # Sends first (up), then last (down); receives below (from down), then
-        # above (from up).  With two ranks up and down are one peer and the
-        # messages pair off in this order (RCCL has no tags); gloo also gets
-        # tags: 1 for rows travelling up, 0 for rows travelling down.
-        ops = [dist.P2POp(dist.isend, first, up, self.group, tag=1),
-               dist.P2POp(dist.isend, last, down, self.group, tag=0),
-               dist.P2POp(dist.irecv, below_x, down, self.group, tag=1),
-               dist.P2POp(dist.irecv, above_x, up, self.group, tag=0)]
-        for req in dist.batch_isend_irecv(ops):
-            req.wait()
-        if self.host_staged:
-            above.copy_(above_x)
-            below.copy_(below_x)
-
-    def sweep_em(self, n: int):
-        """n sweeps of the whole lattice (every rank calls it); returns the
-        lattice's (E, M) after each sweep as a device int64 tensor (n, 2)."""
-        import torch
-        import torch.distributed as dist
-        counts = torch.zeros((max(n, 1), 2), dtype=torch.int64, device=self.device)
-        for k in range(n):
-            for c in (0, 1):
-                ptr = counts[k].data_ptr() if c == 1 else None
-                check(lib().ising_strip_step(self.h, c, self.t + k, ptr))
-                self._exchange(c)
-        if self.host_staged:
-            host = counts.cpu()
-            dist.all_reduce(host, group=self.group)
-            counts.copy_(host)
-        else:
-            dist.all_reduce(counts, group=self.group)
-        EM = torch.empty((max(n, 1), 2), dtype=torch.int64, device=self.device)
-        check(lib().ising_strip_combine(counts.data_ptr(), 1, n, self.L, EM.data_ptr(),
-                                        _stream_ptr(self.stream)))
-        self.t += n
-        return EM[:n]
-
-    def get_rows(self):
-        """This rank's rows as int8 (rows x L)."""
-        import numpy as np
-        out = np.empty((self.rows, self.L), dtype=np.int8)
-        check(lib().ising_strip_get_rows(self.h, out.ctypes.data))
         return out
 
 
@@ -587,7 +472,16 @@ def multi_sweep(lattices: Sequence[Lattice], n: int, EMs=None, form=None, graph_
         em_arr = (ctypes.c_void_p * max(len(lattices), 1))(
             *[(e.data_ptr() if e is not None else None) for e in EMs])
     f = {None: -1, "fused": 0, "packed": 1}[form]
-    check(lib().ising_multi_sweep_form(arr, len(lattices), int(n), em_arr, f, int(graph_chunk)))
+    nbytes = ctypes.c_size_t()
+    check(lib().ising_multi_sweep_work_bytes(arr, len(lattices), ctypes.byref(nbytes)))
+    work = None
+    if nbytes.value > 0:
+        # the call synchronises the lattices' stream before it returns, so
+        # the work buffer may go back to torch's pool right after it
+        work = _dev_alloc(nbytes.value, lattices[0].device)
+    check(lib().ising_multi_sweep_form(arr, len(lattices), int(n), em_arr, f, int(graph_chunk),
+                                       work.data_ptr() if work is not None else None,
+                                       int(nbytes.value)))
 
 
 def reweight(EMs, betas0, discards, task_lattice, task_beta, nblocks: int, stream=None):
@@ -605,6 +499,11 @@ def reweight(EMs, betas0, discards, task_lattice, task_beta, nblocks: int, strea
             raise IsingError(ISING_EINVAL, "reweight: series must be contiguous int64 (n, 2)")
     sums = torch.empty((max(nt, 1), nblocks, 5), dtype=torch.float64, device=dev)
     shift = torch.empty((max(nt, 1),), dtype=torch.float64, device=dev)
+    work = _dev_alloc(int(lib().ising_reweight_work_bytes(max(nl, 1), max(nt, 1))), dev)
+    # the kernel reads these on stream st after the call returns: tell
+    # torch's allocator, so their memory is not reused before st passes it
+    for t in (sums, shift, work):
+        t.record_stream(st)
     ptrs = (ctypes.c_void_p * max(nl, 1))(*[e.data_ptr() for e in EMs])
     n = (ctypes.c_int64 * max(nl, 1))(*[int(e.shape[0]) for e in EMs])
     d = (ctypes.c_int64 * max(nl, 1))(*[int(v) for v in discards])
@@ -612,7 +511,8 @@ def reweight(EMs, betas0, discards, task_lattice, task_beta, nblocks: int, strea
     tl = (ctypes.c_int32 * max(nt, 1))(*[int(v) for v in task_lattice])
     tb = (ctypes.c_double * max(nt, 1))(*[float(v) for v in task_beta])
     check(lib().ising_reweight(nl, ptrs, n, d, b0, nt, tl, tb, int(nblocks), sums.data_ptr(),
-                               shift.data_ptr(), _stream_ptr(st)))
+                               shift.data_ptr(), work.data_ptr(), int(work.numel()),
+                               _stream_ptr(st)))
     return sums, shift
 
 

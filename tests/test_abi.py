@@ -182,6 +182,8 @@ def test_server_validation_before_device_work(L):
     assert L.ising_server_create(ctypes.c_void_p((1 << 20) + 8), 1 << 20, None, 4,
                                  ctypes.byref(s)) == -1  # not 256-byte aligned
     assert L.ising_server_create(arena, 1 << 20, None, 0, ctypes.byref(s)) == -1
+    # the table region takes at least 4 KiB and at most half of the arena
+    assert L.ising_server_create(arena, 4096, None, 4, ctypes.byref(s)) == -1
     assert L.ising_server_step(None) == -1
     assert L.ising_batch_submit(None, None, 0, None) == -1
     assert L.ising_poll(None, 1, None) == -1
@@ -190,22 +192,33 @@ def test_server_validation_before_device_work(L):
 
 
 def test_batch_and_reweight_validation_before_device_work(L):
-    assert L.ising_multi_sweep(None, 1, 1, None) == -1
+    assert L.ising_multi_sweep(None, 1, 1, None, None, 0) == -1
     two = (ctypes.c_void_p * 2)(None, None)
-    assert L.ising_multi_sweep(two, 2, 1, None) == -1  # NULL handles
-    assert L.ising_multi_sweep(two, -1, 1, None) == -1
-    assert L.ising_multi_sweep_form(None, 1, 1, None, 0, -1) == -1
+    assert L.ising_multi_sweep(two, 2, 1, None, None, 0) == -1  # NULL handles
+    assert L.ising_multi_sweep(two, -1, 1, None, None, 0) == -1
+    assert L.ising_multi_sweep_form(None, 1, 1, None, 0, -1, None, 0) == -1
+    nb = ctypes.c_size_t(7)
+    assert L.ising_multi_sweep_work_bytes(two, 2, ctypes.byref(nb)) == -1 and nb.value == 0
+    assert L.ising_multi_sweep_work_bytes(two, 0, None) == -1
     i64 = ctypes.c_int64
     f64 = ctypes.c_double
     em = (ctypes.c_void_p * 1)(4096)  # never dereferenced
     nsw, disc, b0 = (i64 * 1)(100), (i64 * 1)(20), (f64 * 1)(0.44)
     tl, tb = (ctypes.c_int32 * 1)(0), (f64 * 1)(0.45)
     sums = ctypes.c_void_p(8192)
+    work = ctypes.c_void_p(1 << 16)  # 256-byte aligned, never dereferenced
+    need = int(L.ising_reweight_work_bytes(1, 1))
+    assert need >= 256 + 16 and L.ising_reweight_work_bytes(0, 1) == 0
+    assert L.ising_reweight_work_bytes(3, 1000) >= 1000 * 16
 
     def rw(nlat=1, em=em, nsw=nsw, disc=disc, b0=b0, ntask=1, tl=tl, tb=tb, nblocks=20,
-           sums=sums):
+           sums=sums, work=work, nwork=need):
         return L.ising_reweight(nlat, em, nsw, disc, b0, ntask, tl, tb, nblocks, sums, None,
-                                None)
+                                work, nwork, None)
+
+    assert rw(work=None) == -2
+    assert rw(work=ctypes.c_void_p((1 << 16) + 8)) == -2  # misaligned
+    assert rw(nwork=need - 1) == -2
 
     assert rw(nlat=0) == -1
     assert rw(ntask=0) == -1

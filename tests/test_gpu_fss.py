@@ -81,6 +81,31 @@ def test_reweight_matches_oracle_on_seeded_series(I):
             _check_sums(sums[k], want, host[i][discards[i]:, 0])
 
 
+def test_reweight_on_two_streams(I):
+    """Two reweights in flight at once on two streams, each with its own
+    caller-owned work buffer; both match the oracle."""
+    import torch
+    rng = np.random.default_rng(77)
+    host = [_series(rng, 64, 3001), _series(rng, 128, 2500)]
+    EMs = [torch.tensor(h, device="cuda") for h in host]
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    torch.cuda.synchronize()
+    jobs = [(s1, 0, [0.41, 0.45, 0.43]), (s2, 1, [0.39, 0.40])]
+    out = []
+    for st, i, betas in jobs:
+        _say("case stream %d" % i)
+        tl = [0] * len(betas)
+        out.append(I.reweight([EMs[i]], [0.42], [300], tl, betas, 9, stream=st))
+    torch.cuda.synchronize()
+    for (st, i, betas), (sums, shift) in zip(jobs, out):
+        sums = sums.cpu().numpy()
+        shift = shift.cpu().numpy()
+        for k, b in enumerate(betas):
+            want, wshift = fss.reweight_sums(host[i][:, 0], host[i][:, 1], 300, 0.42, b, 9)
+            assert shift[k] == wshift
+            _check_sums(sums[k], want, host[i][300:, 0])
+
+
 def test_reweight_argument_checks(I):
     import torch
     EM = torch.zeros((10, 2), dtype=torch.int64, device="cuda")
