@@ -109,3 +109,29 @@ def crossing_jackknife(T, Ua, Ub, Ua_rep, Ub_rep):
     mean = reps.mean(axis=0)
     err = np.sqrt((B - 1) / B * ((reps - mean) ** 2).sum(axis=0))
     return Tx, Ux, float(err[0]), float(err[1])
+
+
+def autocorr_time(x, c=5.0):
+    """Integrated autocorrelation time of a series, with the automatic
+    window of A. D. Sokal (Monte Carlo methods in statistical mechanics,
+    Cargese lectures 1996, section 3): with the sample mean removed,
+      C(t) = sum_{i < n - t} y_i y_{i+t} / (n - t),  rho(t) = C(t) / C(0),
+      tau(W) = 1/2 + sum_{t=1}^{W} rho(t),
+    and W the smallest window in 1 .. floor(n / 2) with W >= c tau(W).
+    Returns (tau(W), W); (tau(floor(n / 2)), -1) when no window qualifies
+    (the series is too short for its correlations); (0.5, 0) for a constant
+    series.  The error of a mean of n samples is then sqrt(2 tau C(0) / n)."""
+    y = np.asarray(x, dtype=np.float64)
+    n = len(y)
+    if n < 2:
+        raise ValueError("need at least two samples")
+    y = y - y.mean()
+    c0 = float(np.dot(y, y)) / n
+    if c0 == 0.0:
+        return 0.5, 0
+    tau = 0.5
+    for W in range(1, n // 2 + 1):
+        tau += float(np.dot(y[:n - W], y[W:])) / (n - W) / c0
+        if W >= c * tau:
+            return tau, W
+    return tau, -1
