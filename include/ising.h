@@ -455,6 +455,23 @@ ISING_API ising_status ising_binder_crossing(const double *T, int32_t K, const d
                                              const double *Ub_rep, int32_t nblocks,
                                              double *out);
 
+/*
+ * Integrated autocorrelation time of a series x[0 .. n-1] (host, n >= 2),
+ * the measure of how many sweeps separate independent samples, which the
+ * errors of the Binder-cumulant analysis (section 2, Eq. (2)) need: kept
+ * blocks must be long against it.  With y = x - mean,
+ * C(t) = sum_{i < n-t} y_i y_{i+t} / (n - t), rho(t) = C(t) / C(0) and
+ * tau(W) = 1/2 + sum_{t=1..W} rho(t), the window W is the smallest in
+ * 1 .. floor(n/2) with W >= c tau(W) (A. D. Sokal's automatic window;
+ * c = 5 is usual).  *tau = tau(W), *window = W; *window = -1 when no
+ * window qualifies (*tau is then tau(floor(n/2)): the series is too short
+ * for its correlations); a constant series gives 0.5 and 0.  The sums
+ * C(t) are formed by FFT in fp64.  n <= 2^28.  Errors: EINVAL (NULL
+ * pointers, n < 2, c <= 0, a non-finite sample).
+ */
+ISING_API ising_status ising_autocorr_time(const double *x, int64_t n, double c, double *tau,
+                                           int64_t *window);
+
 /* ---------------------------------------------------------------- */
 /* Served mode: continuous batching of independent simulations.      */
 /* ---------------------------------------------------------------- */

@@ -22,6 +22,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <complex>
 #include <cstring>
 #include <limits>
 #include <vector>
@@ -152,6 +153,33 @@ void crossing(const double* T, int K, const double* Ua, const double* Ub, double
   }
 }
 
+// In-place radix-2 FFT of a (size a power of two) with the twiddles
+// exp(-2 pi i k / n) taken from a table computed directly (no accumulated
+// rotation), sign +1 for the inverse transform (unscaled).
+void fft(std::vector<std::complex<double>>& a, int sign) {
+  const size_t n = a.size();
+  std::vector<std::complex<double>> tw(n / 2);
+  for (size_t k = 0; k < n / 2; ++k) {
+    const double ang = sign * 2.0 * M_PI * (double)k / (double)n;
+    tw[k] = std::complex<double>(std::cos(ang), std::sin(ang));
+  }
+  for (size_t i = 1, j = 0; i < n; ++i) {
+    size_t bit = n >> 1;
+    for (; j & bit; bit >>= 1) j ^= bit;
+    j ^= bit;
+    if (i < j) std::swap(a[i], a[j]);
+  }
+  for (size_t len = 2; len <= n; len <<= 1) {
+    const size_t half = len / 2, step = n / len;
+    for (size_t i = 0; i < n; i += len)
+      for (size_t j = 0; j < half; ++j) {
+        const std::complex<double> u = a[i + j], v = a[i + j + half] * tw[j * step];
+        a[i + j] = u + v;
+        a[i + j + half] = u - v;
+      }
+  }
+}
+
 }  // namespace
 }  // namespace ising
 
@@ -246,6 +274,53 @@ ising_status ising_fss_moments(const double* sums, int32_t ntask, int32_t nblock
     if (u4_rep)
       for (int32_t b = 0; b < nblocks; ++b) u4_rep[(size_t)k * nblocks + b] = reps[3 * (size_t)b];
   }
+  return ISING_OK;
+}
+
+ising_status ising_autocorr_time(const double* x, int64_t n, double c, double* tau,
+                                 int64_t* window) {
+  clear_error();
+  if (!x || n < 2 || !tau || !window || !(c > 0.0) || !std::isfinite(c))
+    return fail(ISING_EINVAL, "ising_autocorr_time: bad arguments (n >= 2, c > 0)");
+  if (n > (int64_t(1) << 28)) return fail(ISING_EINVAL, "ising_autocorr_time: n > 2^28");
+  double mean = 0.0;
+  for (int64_t i = 0; i < n; ++i) {
+    if (!std::isfinite(x[i])) return fail(ISING_EINVAL, "ising_autocorr_time: x[%lld] not finite",
+                                          (long long)i);
+    mean += x[i];
+  }
+  mean /= (double)n;
+  // sums S(t) = sum_{i < n - t} y_i y_{i+t} for all t at once: the inverse
+  // transform of |FFT(y)|^2, zero-padded to avoid wrap-around
+  size_t m = 1;
+  while (m < 2 * (size_t)n) m <<= 1;
+  std::vector<std::complex<double>> a(m, std::complex<double>(0.0, 0.0));
+  double c0 = 0.0;
+  for (int64_t i = 0; i < n; ++i) {
+    const double y = x[i] - mean;
+    a[i] = y;
+    c0 += y * y;
+  }
+  c0 /= (double)n;
+  if (c0 == 0.0) {
+    *tau = 0.5;
+    *window = 0;
+    return ISING_OK;
+  }
+  fft(a, -1);
+  for (size_t k = 0; k < m; ++k) a[k] = std::complex<double>(std::norm(a[k]), 0.0);
+  fft(a, +1);
+  double t = 0.5;
+  for (int64_t W = 1; W <= n / 2; ++W) {
+    t += a[W].real() / (double)m / (double)(n - W) / c0;
+    if ((double)W >= c * t) {
+      *tau = t;
+      *window = W;
+      return ISING_OK;
+    }
+  }
+  *tau = t;
+  *window = -1;
   return ISING_OK;
 }
 

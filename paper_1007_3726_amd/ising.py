@@ -133,6 +133,7 @@ def lib():
                             P(ctypes.c_double), i32, vp, vp, vp, ctypes.c_size_t, vp], i32),
         "ising_reweight_work_bytes": ([i32, i32], ctypes.c_size_t),
         "ising_fss_moments": ([vp, i32, i32, P(i64), vp, vp, vp], i32),
+        "ising_autocorr_time": ([vp, i64, ctypes.c_double, P(ctypes.c_double), P(i64)], i32),
         "ising_binder_crossing": ([vp, i32, vp, vp, vp, vp, i32, vp], i32),
     }
     for name, (args, res) in sig.items():
@@ -530,6 +531,16 @@ def fss_moments(sums, sites):
                                   N.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
                                   est.ctypes.data, err.ctypes.data, rep.ctypes.data))
     return est, err, rep
+
+
+def autocorr_time(x, c: float = 5.0):
+    """(tau, window) of a host series (ising_autocorr_time); window -1 when the
+    series is too short for its correlations."""
+    a = np.ascontiguousarray(x, dtype=np.float64)
+    tau, W = ctypes.c_double(), ctypes.c_int64()
+    check(lib().ising_autocorr_time(a.ctypes.data, int(a.size), float(c), ctypes.byref(tau),
+                                    ctypes.byref(W)))
+    return float(tau.value), int(W.value)
 
 
 def binder_crossing(T, Ua, Ub, Ua_rep=None, Ub_rep=None):

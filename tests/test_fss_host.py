@@ -70,3 +70,45 @@ def test_moments_argument_checks(I):
         I.fss_moments(np.ones((2, 1, 5)), [16, 16])  # one block: no jackknife
     with pytest.raises(I.IsingError):
         I.fss_moments(np.ones((2, 3, 5)), [16, 0])
+
+
+def _ar1(phi, n, seed):
+    rng = np.random.default_rng(seed)
+    e = rng.standard_normal(n)
+    x = np.empty(n)
+    x[0] = e[0]
+    s = math.sqrt(1.0 - phi * phi)
+    for i in range(1, n):
+        x[i] = phi * x[i - 1] + s * e[i]
+    return x
+
+
+@pytest.mark.parametrize("phi,n,c", [(0.0, 5000, 5.0), (0.7, 30000, 5.0), (0.95, 60000, 5.0),
+                                     (0.95, 60000, 8.0), (0.999, 3000, 5.0)])
+def test_autocorr_time_matches_the_oracle(I, phi, n, c):
+    """The library forms C(t) by FFT, the oracle by direct sums: tau agrees to
+    rounding (far below its statistical error) and the window exactly."""
+    x = 1000.0 + 37.0 * _ar1(phi, n, int(phi * 1000) + n)
+    got = I.autocorr_time(x, c)
+    want = fss.autocorr_time(x, c)
+    assert got[1] == want[1]
+    assert abs(got[0] - want[0]) <= 1e-9 * max(1.0, abs(want[0]))
+
+
+def test_autocorr_time_on_magnetisation_like_series(I):
+    """Integer series of the kind the sweeps write (M^2 of a 64 x 64 lattice)."""
+    rng = np.random.default_rng(5)
+    M = np.cumsum(2 * rng.integers(-3, 4, size=20000)) % 4096 - 2048
+    x = (M.astype(np.float64)) ** 2
+    got = I.autocorr_time(x)
+    want = fss.autocorr_time(x)
+    assert got[1] == want[1] and abs(got[0] - want[0]) <= 1e-9 * max(1.0, abs(want[0]))
+    assert I.autocorr_time(np.full(7, 2.0)) == (0.5, 0)
+    assert I.autocorr_time(np.array([1.0, -1.0] * 8))[1] == 1
+
+
+def test_autocorr_time_argument_checks(I):
+    for bad in (([1.0], 5.0), ([1.0, 2.0], 0.0), ([1.0, 2.0], float("nan")),
+                ([1.0, float("inf")], 5.0)):
+        with pytest.raises(I.IsingError):
+            I.autocorr_time(*bad)
