@@ -1,27 +1,38 @@
 """Benchmark of the checkerboard Metropolis sweep on one MI355X.
 
-One step = one pass of the hot path over the 16384 x 16384 lattice at
-T = 2.269185 (cold start, packed 64 spins per word): 2000 full sweeps with
-exact per-sweep int64 (E, M), the lattice resident in HBM.  The timed region
-covers exactly `--steps` steps between two synchronisations; value is spin
-updates per ns (N * sweeps / time).
+One step = one pass of the hot path over the HBM-resident 262144 x 262144
+lattice (6.9e10 spins, 8 GiB packed 64 spins per word) at T = 2.0 from a hot
+start (seed 7): 100 full sweeps with exact per-sweep int64 (E, M).  The
+timed region covers exactly `--steps` steps between two synchronisations;
+value is spin updates per ns (N * sweeps / time).
 
 Also reported on the same JSON line:
-  roofline      - the half-sweep kernel against the integer VALU issue peak;
+  roofline      - the colour-step kernel against the integer VALU issue peak
+                  (its average duration measured with HIP events on the
+                  lattice's stream over the timed region);
   cpu_baseline  - the CPU oracle timed on a bounded sample of the same
-                  workload on this host's cores (a baseline, not the target);
-  lcg, pool     - the plain workload with the paper's own random numbers:
+                  workload (a band of rows of the same lattice, with its
+                  light-cone margins) on this host's cores;
+  configs       - the other plain configurations: the same lattice at
+                  T = 3.0, 16384^2 at T = 2.269185 from a cold start (2000
+                  sweeps, in the 256 MB Infinity Cache), and 64^2 at T = 2.269
+                  (1000 sweeps, its latency);
+  lcg, pool     - the 16384^2 workload with the paper's own random numbers:
                   per-thread LCGs, and Boltzmann-pattern pools read at random
                   addresses or linearly;
   strip_share   - one GPU's share of 262144^2 split over 8 GPUs (a 32768-row
-                  strip with halo rows), its halo exchange, and all eight
-                  strips run here;
+                  strip with halo rows), all eight strips run here;
   table2        - the paper's benchmark point (4096^2 at 0.99 T_C) with every
                   update variant, batched, and the multi-spin CPU baseline;
+  batched       - the 224-lattice finite-size-scaling grid advanced together,
+                  with its Binder-cumulant analysis (crossings only where the
+                  series are long against their autocorrelation times);
+  fss_proof     - long runs of small lattices whose crossing locates T_C;
+  served        - the 2000-request Poisson stream with continuous batching
+                  (aggregate rate, p50/p99 latency) and its first requests
+                  one at a time on the plain path;
   cpu_msc       - the multi-spin-coded CPU baseline (same chain, 64 spins per
-                  word, vectorised Philox) on the same workload, all cores and
-                  one core: the kind of CPU program the paper's speed-ups are
-                  stated against.
+                  word, vectorised Philox) on the 16384^2 lattice.
 
 Usage: python bench.py [--gpus 1] [--steps 5] [--warmup 1]
 """
@@ -53,8 +64,11 @@ def parse():
     p.add_argument("--steps", type=int, default=5)
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--cpu-rows", type=int, default=4096,
+                   help="rows of the lattice in the CPU oracle's sample (a band with light-cone "
+                        "margins, 2 sweeps) for the 262144^2 workloads")
     p.add_argument("--cpu-sweeps", type=int, default=16,
-                   help="sweeps of the 16384^2 lattice the oracle runs for the CPU baseline")
+                   help="sweeps the oracle runs for the CPU baseline of the smaller workloads")
     p.add_argument("--sweeps", type=int, default=None,
                    help="sweeps per step (default: the workload's 2000); for short profiles")
     p.add_argument("--copy-calibration", action="store_true",
@@ -62,10 +76,13 @@ def parse():
     p.add_argument("--no-batched", action="store_true",
                    help="skip the batched finite-size-scaling grid")
     p.add_argument("--batched-sweeps", type=int, default=workloads.FSS_SWEEPS)
-    p.add_argument("--workload", default="large", choices=["large", "huge-T2", "huge-T3", "small",
-                                                           "paper-4096"],
-                   help="plain workload: large = 16384^2 (the headline), huge = 262144^2 "
-                        "(8 GiB, HBM-resident), small = 64^2, paper-4096 = 4096^2 at 0.99 T_c")
+    p.add_argument("--workload", default="huge-T2",
+                   choices=["large", "huge-T2", "huge-T3", "small", "paper-4096"],
+                   help="plain workload: huge = 262144^2 (8 GiB, HBM-resident; T2 is the "
+                        "headline), large = 16384^2, small = 64^2, paper-4096 = 4096^2 at "
+                        "0.99 T_c")
+    p.add_argument("--no-configs", action="store_true",
+                   help="skip the other plain configurations")
     p.add_argument("--no-served", action="store_true", help="skip the served request stream")
     p.add_argument("--no-cpu-msc", action="store_true",
                    help="skip the multi-spin-coded CPU baseline")
@@ -79,21 +96,23 @@ def parse():
                    help="skip the plain workload with Boltzmann-pattern pools")
     p.add_argument("--no-autotune", action="store_true",
                    help="skip the autotuner report (profiling runs: no trial launches)")
-    p.add_argument("--served-requests", type=int, default=200,
-                   help="requests of the 2000-request Poisson stream to serve (default: the "
-                        "first 200, about 20 s)")
+    p.add_argument("--served-requests", type=int, default=2000,
+                   help="requests of the 2000-request Poisson stream to serve (default: all, "
+                        "about 160 s)")
     p.add_argument("--served-arena-gib", type=float, default=1.0)
     p.add_argument("--served-quantum", type=int, default=400)
-    p.add_argument("--plain-fifo-requests", type=int, default=20,
+    p.add_argument("--plain-fifo-requests", type=int, default=200,
                    help="requests of the same stream run one by one with the plain path")
     return p.parse_args()
 
 
-def bench_served(torch, ising, dev, n_req, arena_gib, quantum, plain_n, plain_rate):
+def bench_served(torch, ising, dev, n_req, arena_gib, quantum, plain_n, plain_rate, cap_n=300):
     """Poisson stream of requests (L log-uniform in [32, 8192], T uniform in
     [1.5, 3.5], sweeps log-uniform in [1e3, 1e5], seed 1000 + i, hot start)
     served with continuous batching; arrival rate 0.7 x the plain throughput
-    divided by the mean work per request (1.30e11 spin updates)."""
+    divided by the mean work per request (1.30e11 spin updates).  Also the
+    server's capacity on the stream's first cap_n requests queued at once,
+    and the first plain_n requests run one at a time on the plain path."""
     import numpy as np
     rate = 0.7 * plain_rate * 1e9 / 1.30e11
     stream = workloads.served_stream(2000, rate=rate)[:n_req]
@@ -144,6 +163,26 @@ def bench_served(torch, ising, dev, n_req, arena_gib, quantum, plain_n, plain_ra
            "mean_latency_s": round(float(lat.mean()), 3),
            "wall_s": round(wall, 3), "arena_gib": arena_gib, "quantum_sweeps": quantum,
            "peak_arena_bytes": stats["peak_bytes"], "quanta": stats["quanta"]}
+    # capacity: the first requests of the stream all queued at once, so the
+    # server never waits for an arrival
+    if cap_n > 0:
+        print("bench: served capacity (%d requests queued at once)" % cap_n, file=sys.stderr,
+              flush=True)
+        sub = stream[:cap_n]
+        srv = ising.Server(int(arena_gib * (1 << 30)), quantum_sweeps=quantum, device=dev)
+        reqs = [{"L": r.L, "beta": 1.0 / r.T, "seed": r.seed, "stream_id": r.stream_id,
+                 "init": r.init, "n_sweeps": r.sweeps, "n_discard": r.sweeps // 5} for r in sub]
+        torch.cuda.synchronize()
+        tc = time.perf_counter()
+        tickets = srv.submit(reqs)
+        srv.run_until_idle()
+        dtc = time.perf_counter() - tc
+        done = [srv.poll(t) for t in tickets]
+        assert all(d is not None for d in done)
+        srv.close()
+        cwork = sum(r.L * r.L * r.sweeps for r in sub)
+        out["capacity"] = {"requests": cap_n, "value": round(cwork / (dtc * 1e9), 2),
+                           "seconds": round(dtc, 3)}
     # the same requests one at a time through the plain path (FIFO, no overlap)
     if plain_n > 0:
         sub = stream[:plain_n]
@@ -231,8 +270,49 @@ def binder_exact(M, discard):
     return float(1 - Fraction(s4 * n, 3 * s2 * s2)) if s2 else float("nan")
 
 
+# A series supports an error estimate (the reading taken here; the paper
+# gives none) when Sokal's window converged, each of the jackknife blocks
+# spans at least BLOCK_TAUS integrated autocorrelation times of M^2, and the
+# discarded start spans at least DISCARD_TAUS of them.
+BLOCK_TAUS = 10.0
+DISCARD_TAUS = 20.0
+
+
+def series_check(ising, M, discard, nblocks):
+    """(ok, tau, window) for the kept part of an int64 magnetisation series."""
+    kept = np.asarray(M[discard:], dtype=np.float64)
+    tau, W = ising.autocorr_time(kept * kept)
+    per_block = len(kept) / nblocks
+    ok = W > 0 and per_block >= BLOCK_TAUS * tau and discard >= DISCARD_TAUS * tau
+    return bool(ok), float(tau), int(W)
+
+
+def crossings_where_resolved(ising, sizes, checks, fine, curves):
+    """Binder crossings of adjacent sizes, reported only where every run of
+    both sizes passes series_check; otherwise the reason."""
+    out = {}
+    for x, y in zip(sizes[:-1], sizes[1:]):
+        key = "%d/%d" % (x, y)
+        bad = [(L, c) for L in (x, y) for c in checks[L] if not c[0]]
+        if bad:
+            worst = max(bad, key=lambda v: v[1][1])
+            out[key] = {"resolved": False,
+                        "reason": "%d of %d runs too short for their autocorrelation "
+                                  "(largest tau_int of M^2: %.0f sweeps at L=%d)"
+                                  % (len(bad), len(checks[x]) + len(checks[y]), worst[1][1],
+                                     worst[0])}
+            continue
+        t, u, et, eu = ising.binder_crossing(fine, curves[x][0][:, 0], curves[y][0][:, 0],
+                                             curves[x][2], curves[y][2])
+        out[key] = {"resolved": True, "T": round(t, 5), "T_err": round(et, 5),
+                    "U4": round(u, 4), "U4_err": round(eu, 4)}
+    return out
+
+
 def bench_batched(torch, ising, dev, sweeps):
-    """224 lattices (L in 64..4096 x 32 temperatures) in one persistent launch."""
+    """224 lattices (L in 64..4096 x 32 temperatures) advanced together:
+    two fused launches per sweep over all lattices, replayed from captured
+    hipGraph chunks."""
     grid = workloads.fss_grid()
     lats = [ising.Lattice(g.L, seed=g.seed, stream_id=g.stream_id, init=g.init, beta=1.0 / g.T,
                           device=dev) for g in grid]
@@ -250,19 +330,24 @@ def bench_batched(torch, ising, dev, sweeps):
     plain_sweeps = max(1, min(sweeps, 500))
     seq = [ising.Lattice(g.L, seed=g.seed, stream_id=g.stream_id, init=g.init, beta=1.0 / g.T,
                          device=dev) for g in grid]
+    plain_EMs = [torch.empty((plain_sweeps, 2), dtype=torch.int64, device=dev) for _ in grid]
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    for lat, em in zip(seq, EMs):
-        lat.sweep(plain_sweeps, em[:plain_sweeps])
+    for lat, em in zip(seq, plain_EMs):
+        lat.sweep(plain_sweeps, em)
     torch.cuda.synchronize()
     dt_plain = time.perf_counter() - t1
     plain_updates = sum(g.L * g.L for g in grid) * plain_sweeps
+    for em, pem in zip(EMs, plain_EMs):
+        assert torch.equal(em[:plain_sweeps], pem), "batched and plain series differ"
+    del seq, plain_EMs
     tidx = [0, len(workloads.FSS_TEMPS) // 2, len(workloads.FSS_TEMPS) - 1]
     fss = bench_fss(torch, ising, dev, grid, EMs, discard)
     return {
         "value": round(updates / (dt * 1e9), 2), "unit": "spin updates/ns",
         "workload": "224 lattices, L in {64..4096} x 32 T in [2.20, 2.34], hot start, "
-                    "%d sweeps each, per-sweep int64 E/M, one persistent launch" % sweeps,
+                    "%d sweeps each, per-sweep int64 E/M; two fused launches per sweep over "
+                    "all lattices, replayed from hipGraph chunks" % sweeps,
         "seconds": round(dt, 3),
         "plain_one_by_one": {"value": round(plain_updates / (dt_plain * 1e9), 2),
                              "sweeps": plain_sweeps},
@@ -274,9 +359,10 @@ def bench_batched(torch, ising, dev, sweeps):
 
 
 def bench_fss(torch, ising, dev, grid, EMs, discard, per_interval=8, nblocks=20):
-    """Binder-cumulant crossings of adjacent sizes of the batched grid: the
-    series are reweighted on the device to a grid 8x finer than the simulated
-    temperatures (each point from the nearest run), with jackknife errors."""
+    """Binder cumulants of the batched grid reweighted on the device to a
+    grid 8x finer than the simulated temperatures (each point from the
+    nearest run), with jackknife errors; crossings of adjacent sizes only
+    where the series are long against their autocorrelation times."""
     temps = np.array([g.T for g in grid])
     Ls = [g.L for g in grid]
     T_lo, T_hi = float(temps.min()), float(temps.max())
@@ -300,19 +386,21 @@ def bench_fss(torch, ising, dev, grid, EMs, discard, per_interval=8, nblocks=20)
     rw_ms = a.elapsed_time(b)
     t0 = time.perf_counter()
     curves = ising.binder_curves(EMs, Ls, temps, discard, fine, nblocks, stream)
+    checks = {}
+    for L, em in zip(Ls, EMs):
+        checks.setdefault(L, []).append(series_check(ising, em[:, 1].cpu().numpy(), discard,
+                                                     nblocks))
     sizes = sorted(curves)
-    cross = {}
-    for x, y in zip(sizes[:-1], sizes[1:]):
-        t, u, et, eu = ising.binder_crossing(fine, curves[x][0][:, 0], curves[y][0][:, 0],
-                                             curves[x][2], curves[y][2])
-        cross["%d/%d" % (x, y)] = {"T": round(t, 5), "T_err": round(et, 5), "U4": round(u, 4),
-                                   "U4_err": round(eu, 4)}
+    cross = crossings_where_resolved(ising, sizes, checks, fine, curves)
     chain_s = time.perf_counter() - t0
     samples = EMs[0].shape[0] - discard
     return {"grid_points": len(fine), "tasks": len(tl), "samples_per_task": int(samples),
             "nblocks": nblocks, "reweight_ms": round(rw_ms, 3),
             "reweight_samples_per_s": round(len(tl) * samples / (rw_ms * 1e-3), 1),
-            "analysis_s": round(chain_s, 3), "crossings": cross,
+            "analysis_s": round(chain_s, 3),
+            "tau_int_M2_max": {str(L): round(max(c[1] for c in checks[L]), 1) for L in sizes},
+            "runs_resolved": {str(L): sum(c[0] for c in checks[L]) for L in sizes},
+            "crossings": cross,
             "tc_exact": round(2.0 / math.log(1.0 + math.sqrt(2.0)), 6)}
 
 
@@ -506,7 +594,8 @@ def bench_strip_share(torch, ising, dev, nstrips=8, sweeps=3):
 def bench_fss_proof(torch, ising, dev, sweeps=200_000, discard=20_000, nblocks=20):
     """The paper's proof of concept (section 2): Binder cumulants of small
     lattices (L = 8..64, six temperatures in [2.15, 2.40], long runs on the
-    batched path) cross near T_C."""
+    batched path) cross near T_C; crossings only where the series are long
+    against their autocorrelation times."""
     temps = np.linspace(2.15, 2.40, 6)
     sizes = (8, 16, 32, 64)
     lats, EMs, Ls, T_all = [], [], [], []
@@ -523,16 +612,16 @@ def bench_fss_proof(torch, ising, dev, sweeps=200_000, discard=20_000, nblocks=2
     dt = time.perf_counter() - t0
     fine = np.linspace(2.15, 2.40, 51)
     curves = ising.binder_curves(EMs, Ls, T_all, discard, fine, nblocks)
-    cross = {}
-    for x, y in zip(sizes[:-1], sizes[1:]):
-        t, u, et, eu = ising.binder_crossing(fine, curves[x][0][:, 0], curves[y][0][:, 0],
-                                             curves[x][2], curves[y][2])
-        cross["%d/%d" % (x, y)] = {"T": round(t, 5), "T_err": round(et, 5), "U4": round(u, 4),
-                                   "U4_err": round(eu, 4)}
+    checks = {}
+    for L, em in zip(Ls, EMs):
+        checks.setdefault(L, []).append(series_check(ising, em[:, 1].cpu().numpy(), discard,
+                                                     nblocks))
+    cross = crossings_where_resolved(ising, list(sizes), checks, fine, curves)
     return {"workload": "L in {8,16,32,64} x 6 T in [2.15, 2.40], hot start, %d sweeps, "
                         "discard %d" % (sweeps, discard),
             "seconds": round(dt, 3),
             "updates_per_ns": round(sum(L * L for L in Ls) * sweeps / (dt * 1e9), 2),
+            "tau_int_M2_max": {str(L): round(max(c[1] for c in checks[L]), 1) for L in sizes},
             "crossings": cross,
             "tc_exact": round(2.0 / math.log(1.0 + math.sqrt(2.0)), 6)}
 
@@ -577,14 +666,39 @@ def cpu_msc(w, gpu_value, seconds=2.0):
             "gpu_over_cpu": round(gpu_value / ups, 1)}
 
 
-def cpu_baseline(w, sweeps):
+def cpu_baseline(w, sweeps, band_rows):
+    """The CPU oracle on a bounded sample of workload w, on this host's cores.
+    For lattices too large for it to hold (262144^2 would take 69 GB at one
+    byte per spin) the sample is a band of rows of the same lattice simulated
+    with its light-cone margins (oracle.band_em, 2 sweeps from the start);
+    the rate counts the sites swept, and the time of the start alone (the
+    same call with no sweeps) is taken off."""
     import oracle
     threads = oracle.get_threads()
-    s = oracle.init(w.L, w.seed, w.stream_id, w.init)
-    t0 = time.perf_counter()
-    oracle.sweeps(s, 1.0 / w.T, w.seed, w.stream_id, 0, sweeps, record=True)
-    dt = time.perf_counter() - t0
-    ups = w.L * w.L * sweeps / (dt * 1e9)
+    kind = ["cold +1", "cold -1", "hot"][w.init]
+    if w.L > 65536:
+        n = 2
+        rows = min(band_rows, w.L - 2 * (2 * n + 1))
+        t0 = time.perf_counter()
+        oracle.band_em(w.L, 1.0 / w.T, w.seed, w.stream_id, w.init, 0, 0, 0, rows)
+        t_start = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        oracle.band_em(w.L, 1.0 / w.T, w.seed, w.stream_id, w.init, 0, n, 0, rows)
+        dt = time.perf_counter() - t0 - t_start
+        swept = (rows + 2 * (2 * n + 1) - 2) * w.L * n
+        ups = swept / (dt * 1e9)
+        sample = ("%d sweeps of rows 0..%d of the %dx%d lattice (%s start, T=%r) with their "
+                  "%d-row light-cone margins: %.2e site updates in %.1f s (the start, %.1f s, "
+                  "not counted)" % (n, rows - 1, w.L, w.L, kind, w.T, 2 * n + 1, swept, dt,
+                                    t_start))
+    else:
+        s = oracle.init(w.L, w.seed, w.stream_id, w.init)
+        t0 = time.perf_counter()
+        oracle.sweeps(s, 1.0 / w.T, w.seed, w.stream_id, 0, sweeps, record=True)
+        dt = time.perf_counter() - t0
+        ups = w.L * w.L * sweeps / (dt * 1e9)
+        sample = "%d sweeps of the %dx%d lattice (%s start, T=%r), %.1f s" % (
+            sweeps, w.L, w.L, kind, w.T, dt)
     # the paper's benchmark point (Table 2's "CPU simple" row: one byte per
     # spin), all cores and one core
     p = workloads.PAPER_POINT
@@ -600,12 +714,60 @@ def cpu_baseline(w, sweeps):
     finally:
         oracle.set_threads(threads)
     return {"value": ups, "unit": "spin updates/ns", "cores": threads, "kind": "oracle",
-            "sample": "%d sweeps of the %dx%d lattice (%s start, T=%r), %.1f s"
-                      % (sweeps, w.L, w.L, ["cold +1", "cold -1", "hot"][w.init], w.T, dt),
-            "cpu_model": cpu_model(),
+            "sample": sample, "cpu_model": cpu_model(),
             "paper_point": {"workload": "%dx%d, T = 0.99 T_C, 10 sweeps (all cores), 2 sweeps "
                                         "(one core)" % (p.L, p.L),
                             "value": round(paper_all, 4), "value_1core": round(paper_one, 4)}}
+
+
+def time_plain(torch, ising, dev, stream, w, steps, warmup, check=True):
+    """w.sweeps sweeps per step with per-sweep E/M on a fresh lattice: warm-up
+    steps, then `steps` steps timed with HIP events on the lattice's stream.
+    Returns (ms for the timed steps, wall seconds, the lattice, its E/M buffer)."""
+    lat = ising.Lattice(w.L, seed=w.seed, stream_id=w.stream_id, init=w.init, beta=1.0 / w.T,
+                        device=dev, stream=stream)
+    EM = torch.empty((w.sweeps, 2), dtype=torch.int64, device=dev)
+    for _ in range(warmup):
+        lat.sweep(w.sweeps, EM)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    t_wall = time.perf_counter()
+    start.record(stream)
+    for _ in range(steps):
+        lat.sweep(w.sweeps, EM)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_wall
+    ms = start.elapsed_time(stop)
+    if check:
+        # the last step's final (E, M) against an independent recount
+        assert tuple(EM[-1].cpu().tolist()) == lat.measure(), "fused E/M disagrees with a recount"
+    return ms, wall, lat, EM
+
+
+def bench_configs(torch, ising, dev, stream, head):
+    """The other plain configurations, each on a fresh lattice."""
+    out = {}
+    others = [(workloads.HUGE_T3, 2, 1), (workloads.LARGE, 5, 1), (workloads.SMALL, 20, 2)]
+    for w, steps, warmup in others:
+        if w == head:
+            continue
+        print("bench: plain %s (%d steps)" % (w.name, steps), file=sys.stderr, flush=True)
+        ms, _, lat, EM = time_plain(torch, ising, dev, stream, w, steps, warmup)
+        N = w.L * w.L
+        out[w.name] = {"value": round(N * w.sweeps * steps / (ms * 1e6), 2),
+                       "unit": "spin updates/ns",
+                       "workload": "%dx%d, T=%r, %s start, %d sweeps per run with per-sweep "
+                                   "int64 E/M" % (w.L, w.L, w.T,
+                                                  ["cold +1", "cold -1", "hot"][w.init],
+                                                  w.sweeps),
+                       "ms_per_run": round(ms / steps, 3),
+                       "us_per_sweep": round(ms * 1e3 / (steps * w.sweeps), 3),
+                       "form": plain_kernel(ising, w.L, ising.tuning_lookup(w.L))}
+        del lat, EM
+        torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -625,11 +787,8 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream(dev)
-    # the autotuner picks the launch shape for this lattice size (well under a
-    # second; a few seconds for 262144^2)
-    # the headline runs the default launch shape (the one the committed
-    # rocprofv3 summaries cover); the autotuner's pick for this side is
-    # timed and reported beside it, then removed again
+    # the headline runs the library's built-in launch shape; the autotuner's
+    # pick for this side is timed and reported beside it, then removed again
     autotuned = None
     if not args.no_autotune:
         t_at = time.perf_counter()
@@ -641,37 +800,22 @@ def main():
                      "updates_per_ns": round(pick["updates_per_ns"], 1),
                      "seconds": round(time.perf_counter() - t_at, 3)}
         ising.tuning_clear()
+        torch.cuda.empty_cache()
     tuned = ising.tuning_lookup(w.L)
     kernel = plain_kernel(ising, w.L, tuned)
-    lat = ising.Lattice(w.L, seed=w.seed, stream_id=w.stream_id, init=w.init, beta=1.0 / w.T,
-                        device=dev, stream=stream)
-    EM = torch.empty((w.sweeps, 2), dtype=torch.int64, device=dev)
     print("bench: %s L=%d T=%r sweeps/step=%d warmup=%d steps=%d"
           % (w.name, w.L, w.T, w.sweeps, args.warmup, args.steps), file=sys.stderr, flush=True)
-    for _ in range(args.warmup):
-        lat.sweep(w.sweeps, EM)
-    torch.cuda.synchronize()
-    start = torch.cuda.Event(enable_timing=True)
-    stop = torch.cuda.Event(enable_timing=True)
-    t_wall = time.perf_counter()
-    start.record(stream)
-    for _ in range(args.steps):
-        lat.sweep(w.sweeps, EM)
-    stop.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t_wall
-    ms = start.elapsed_time(stop)
+    ms, wall, lat, EM = time_plain(torch, ising, dev, stream, w, args.steps, args.warmup)
     N = w.L * w.L
     updates = N * w.sweeps * args.steps
     value = updates / (ms * 1e6)
-    # consistency check of the last step's final (E, M) against a recount
-    last = EM[-1].cpu().tolist()
-    assert tuple(last) == lat.measure(), "fused E/M disagrees with a recount"
-
     launches = 2 * w.sweeps * args.steps
     launch_us = ms * 1e3 / launches
     ops_per_launch = ALU_OPS_PER_UPDATE * N / 2
     achieved = ops_per_launch / (launch_us * 1e-6)
+    del lat, EM
+    torch.cuda.empty_cache()
+    start_kind = ["cold +1", "cold -1", "hot"][w.init]
     result = {
         "metric": "spin updates/ns (packed checkerboard), batched vs plain; p50/p99 solve latency",
         "value": round(value, 2),
@@ -685,10 +829,10 @@ def main():
         "vs_baseline": None,
         "dtype": "u64",
         "data": "synthetic",
-        "config": {"workload": "plain %dx%d periodic lattice, T=%r, %s start, %d sweeps/step, "
-                               "per-sweep int64 E/M" % (w.L, w.L, w.T,
-                                                        ["cold +1", "cold -1", "hot"][w.init],
-                                                        w.sweeps),
+        "config": {"workload": "plain %dx%d periodic lattice (%.2g spins, %.1f GiB packed), "
+                               "T=%r, %s start from seed %d, %d sweeps/step, per-sweep int64 "
+                               "E/M" % (w.L, w.L, float(N), ising.ising_lattice_bytes(w.L) / 2**30,
+                                        w.T, start_kind, w.seed, w.sweeps),
                    "L": w.L, "T": w.T, "sweeps_per_step": w.sweeps, "form": "plain"},
         "roofline": {"bound": "alu", "achieved": round(achieved / 1e12, 3),
                      "peak": round(VALU_PEAK_LANE_OPS / 1e12, 3), "unit": "Tops/s",
@@ -703,13 +847,17 @@ def main():
                   "lds_resident_bytes": tuned["small_lds_bytes"]},
         "autotuner_pick": autotuned,
     }
+    if not args.no_configs:
+        result["configs"] = bench_configs(torch, ising, dev, stream, w)
+    side = workloads.LARGE if w.L > 65536 else w
+    side_steps = max(1, min(args.steps, 3))
     if not args.no_lcg:
-        print("bench: plain workload with the paper's LCG random numbers", file=sys.stderr,
+        print("bench: %s with the paper's LCG random numbers" % side.name, file=sys.stderr,
               flush=True)
-        result["lcg"] = bench_lcg(torch, ising, dev, w, args.steps)
+        result["lcg"] = bench_lcg(torch, ising, dev, side, side_steps)
     if not args.no_pool:
-        print("bench: plain workload with Boltzmann-pattern pools", file=sys.stderr, flush=True)
-        result["pool"] = bench_pool(torch, ising, dev, w, args.steps)
+        print("bench: %s with Boltzmann-pattern pools" % side.name, file=sys.stderr, flush=True)
+        result["pool"] = bench_pool(torch, ising, dev, side, side_steps)
     if not args.no_strip:
         print("bench: one GPU's share of the row-strip decomposition", file=sys.stderr,
               flush=True)
@@ -729,27 +877,25 @@ def main():
     if not args.no_batched:
         print("bench: batched FSS grid (%d sweeps)" % args.batched_sweeps, file=sys.stderr,
               flush=True)
-        del EM
         result["batched"] = bench_batched(torch, ising, dev, args.batched_sweeps)
         print("bench: FSS proof of concept (small lattices, long runs)", file=sys.stderr,
               flush=True)
         result["fss_proof"] = bench_fss_proof(torch, ising, dev)
+        torch.cuda.empty_cache()
     if not args.no_served:
         print("bench: served stream (%d requests)" % args.served_requests, file=sys.stderr,
               flush=True)
         result["served"] = bench_served(torch, ising, dev, args.served_requests,
                                         args.served_arena_gib, args.served_quantum,
                                         args.plain_fifo_requests, value)
-    if not args.no_cpu_baseline and w.L > 65536:
-        print("bench: no CPU baseline for a %d^2 lattice (the byte-per-spin oracle would need "
-              "%.0f GB)" % (w.L, w.L * w.L / 1e9), file=sys.stderr, flush=True)
-    elif not args.no_cpu_baseline:
-        print("bench: CPU oracle baseline (%d sweeps)" % args.cpu_sweeps, file=sys.stderr,
+    if not args.no_cpu_baseline:
+        print("bench: CPU oracle baseline", file=sys.stderr, flush=True)
+        result["cpu_baseline"] = cpu_baseline(w, args.cpu_sweeps, args.cpu_rows)
+    if not args.no_cpu_msc:
+        print("bench: multi-spin-coded CPU baseline (%s)" % side.name, file=sys.stderr,
               flush=True)
-        result["cpu_baseline"] = cpu_baseline(w, args.cpu_sweeps)
-    if not args.no_cpu_msc and w.L <= 65536:
-        print("bench: multi-spin-coded CPU baseline", file=sys.stderr, flush=True)
-        result["cpu_msc"] = cpu_msc(w, value)
+        result["cpu_msc"] = cpu_msc(side, result["configs"][side.name]["value"]
+                                    if side is not w and "configs" in result else value)
     print(json.dumps(result), flush=True)
 
 

@@ -1,11 +1,13 @@
-"""Batched persistent kernel (ising_multi_sweep) parity.
+"""Batched sweeps (ising_multi_sweep) parity.
 
-Every lattice advanced inside one fused launch must be bit-identical (spins
-and every per-sweep (E, M)) to the same lattice advanced alone with
-ising_sweep, and small members are also checked against the CPU oracle.
-Mixes cover single-workgroup packed lattices, lattices split over many
-workgroups with atomic barriers, partial last words (L % 128 != 0) and
-lattices the tiled layout does not cover (L % 8 != 0, plain fallback).
+Every lattice advanced in the batched launches (two fused launches per
+sweep over the tiles of all lattices, or one packed persistent launch for
+small lattices) must be bit-identical (spins and every per-sweep (E, M)) to
+the same lattice advanced alone with ising_sweep, and small members are
+also checked against the CPU oracle.  Mixes cover single-workgroup packed
+lattices, lattices whose tiles spread over many workgroups, partial last
+words (L % 128 != 0) and lattices the tiled layout does not cover
+(L % 8 != 0, plain fallback).
 """
 import sys
 
