@@ -143,9 +143,10 @@ ISING_API ising_status ising_set_sweep(ising_t *h, uint64_t t);
 ISING_API ising_status ising_get_info(const ising_t *h, int64_t *L, int64_t *words_per_row, void **planes);
 
 /*
- * Device bytes of the work buffer ising_multi_sweep needs for these handles
- * (same conditions on the handles as there; 0 when every lattice takes the
- * plain path).  The bytes depend only on the lattice sides.  Host only.
+ * Device bytes of the work buffer ising_multi_sweep (and
+ * ising_multi_sweep_form, whatever form it forces) needs for these handles
+ * (same conditions on the handles as there; 0 when no lattice can take the
+ * batched kernels).  The bytes depend only on the lattice sides.  Host only.
  */
 ISING_API ising_status ising_multi_sweep_work_bytes(ising_t *const *hs, int32_t count,
                                                     size_t *bytes);

@@ -464,7 +464,11 @@ extern "C" ising_status ising_multi_sweep_work_bytes(ising_t* const* hs, int32_t
   *bytes = 0;
   ising_status st = check_batch(hs, count, 0, "ising_multi_sweep_work_bytes");
   if (st != ISING_OK) return st;
-  *bytes = batch_work_bytes(hs, count, default_batch_options());
+  // every form the caller may force: count each tiled lattice (a lone large
+  // lattice takes the plain path only when the cost model chooses)
+  BatchOptions opt = default_batch_options();
+  opt.force_form = 0;
+  *bytes = batch_work_bytes(hs, count, opt);
   return ISING_OK;
 }
 
