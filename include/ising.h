@@ -220,11 +220,13 @@ typedef struct {
  * LDS-resident single workgroup for small lattices; tiles with rpw in
  * {1, 2, 4} x grid cap in {512, 1024, 2048}; for rows of >= 63 words, strips
  * of {rule, 4, 8, 16, 32} rows x grid cap in {1024, 2048}.  It uses the
- * caller's device buffer (ising_lattice_bytes(L) bytes) as scratch and
- * times trial_sweeps sweeps per shape, installs the fastest for L's size
- * class [2^k, 2^(k+1)) and returns it in *out.  Handles created afterwards
- * use it; results are bit-identical for every shape.  Synchronises the
- * stream.
+ * caller's device buffer as scratch: at least ising_lattice_bytes(L) bytes
+ * (rounded up to 256); with 16 * max(trial_sweeps, 2) bytes more, every
+ * trial also records its per-sweep (E, M) there, as a run with a series
+ * does, and is timed with that cost.  It times trial_sweeps sweeps per
+ * shape, installs the fastest for L's size class [2^k, 2^(k+1)) and returns
+ * it in *out.  Handles created afterwards use it; results are bit-identical
+ * for every shape.  Synchronises the stream.
  */
 ISING_API ising_status ising_autotune(int64_t L, void *dev_buf, size_t dev_bytes, void *hip_stream,
                                       int32_t trial_sweeps, ising_tuning *out);

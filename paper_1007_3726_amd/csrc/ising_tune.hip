@@ -8,6 +8,7 @@
 // The table can be read and written so that callers keep a cache.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <mutex>
 #include <vector>
 
@@ -87,6 +88,13 @@ ising_status ising_autotune(int64_t L, void* dev_buf, size_t dev_bytes, void* hi
   ising_t* h = nullptr;
   ising_status st = ising_create(L, 12345, 0, ISING_INIT_HOT, dev_buf, dev_bytes, hip_stream, &h);
   if (st != ISING_OK) return st;
+  // trials record their per-sweep (E, M) as a caller's run would, when the
+  // buffer has room for the series after the lattice
+  const size_t lat_bytes = (lattice_bytes(L) + 255) / 256 * 256;
+  const int64_t em_sweeps = std::max<int64_t>(trial_sweeps, 2);
+  int64_t* dev_EM = nullptr;
+  if (dev_bytes >= lat_bytes + 16 * (size_t)em_sweeps)
+    dev_EM = (int64_t*)((char*)dev_buf + lat_bytes);
   st = ising_set_beta(h, 1.0 / 2.269185);
   struct Cand {
     Tuning t;
@@ -114,10 +122,10 @@ ising_status ising_autotune(int64_t L, void* dev_buf, size_t dev_bytes, void* hi
         ta.RPW != h->tune.rpw)
       continue;
     h->sweep = 0;
-    st = enqueue_sweeps(h, 2, nullptr);  // warm-up
+    st = enqueue_sweeps(h, 2, dev_EM);  // warm-up
     if (st != ISING_OK) break;
     e = hipEventRecord(a, stream);
-    if (e == hipSuccess) st = enqueue_sweeps(h, trial_sweeps, nullptr);
+    if (e == hipSuccess) st = enqueue_sweeps(h, trial_sweeps, dev_EM);
     if (e == hipSuccess && st == ISING_OK) e = hipEventRecord(b, stream);
     if (e == hipSuccess && st == ISING_OK) e = hipEventSynchronize(b);
     float ms = 0.f;

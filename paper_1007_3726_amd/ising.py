@@ -406,7 +406,8 @@ def autotune(L: int, trial_sweeps: int = 10, device="cuda", stream=None) -> dict
     import torch
     dev = torch.device(device)
     st = stream if stream is not None else torch.cuda.current_stream(dev)
-    nbytes = ising_lattice_bytes(L)
+    # the lattice, then room for the trials' per-sweep (E, M)
+    nbytes = (ising_lattice_bytes(L) + 255) // 256 * 256 + 16 * max(int(trial_sweeps), 2)
     buf = _dev_alloc(nbytes, dev)
     out = ising_tuning()
     check(lib().ising_autotune(int(L), buf.data_ptr(), nbytes, _stream_ptr(st), int(trial_sweeps),
