@@ -170,6 +170,22 @@ ISING_API ising_status ising_multi_sweep(ising_t *const *hs, int32_t count, int6
                                          size_t work_bytes);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * batched sweeps as ising_multi_sweep, bit for bit, with no work buffer.
+ * The task tables go to a static device array of 4 MiB inside the library
+ * (one per GPU, held until the process ends); a batch whose tables need
+ * more is rejected with ENOMEM before any device work.  No hipGraph is
+ * built (instantiation allocates): two kernel launches per sweep, enqueued
+ * directly on the handles' stream.  The call allocates no device memory,
+ * waits for the stream before it returns, and is serialised with other
+ * calls on the same GPU in this process (they share the array).  Errors:
+ * EINVAL, ERANGE, ENOMEM, EDEVICE.
+ */
+ISING_API ising_status ising_multi_sweep_static(ising_t *const *hs, int32_t count, int64_t n,
+                                                int64_t *const *dev_EM);
+
+/*
  * Same as ising_multi_sweep with the launch form chosen by the caller:
  * form -1 lets the cost model choose, 0 forces the fused form (two launches
  * per sweep over the flattened tiles of all lattices, replayed from captured

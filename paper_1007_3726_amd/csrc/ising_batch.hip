@@ -457,6 +457,64 @@ static ising_status check_batch(ising_t* const* hs, int32_t count, int64_t n, co
   return ISING_OK;
 }
 
+// ---------------------------------------------------------------------
+// The allocation-free variant (ising_multi_sweep_static): the task tables
+// live in this file-scope device array instead of a caller work buffer.
+// Each GPU holds its own copy of the array for the life of the process; its
+// device address is looked up once per device (hipGetSymbolAddress) and
+// used from then on, never the array's host-side name.  Calls on one device
+// are serialised by a per-device mutex (each call waits for its stream
+// before it returns), so calls from several threads of a process do not
+// overlap on the array.
+// ---------------------------------------------------------------------
+constexpr size_t kStaticWorkBytes = size_t(4) << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticWorkBytes];
+
+namespace {
+struct StaticScratch {
+  std::mutex m;
+  void* ptr = nullptr;  // device address of `scratch` on this device
+};
+StaticScratch& static_scratch(int device) {
+  static StaticScratch s[64];
+  return s[device & 63];
+}
+}  // namespace
+
+extern "C" ising_status ising_multi_sweep_static(ising_t* const* hs, int32_t count, int64_t n,
+                                                 int64_t* const* dev_EM) {
+  clear_error();
+  ising_status st = check_batch(hs, count, n, "ising_multi_sweep_static");
+  if (st != ISING_OK) return st;
+  if (count == 0 || n == 0) return ISING_OK;
+  BatchOptions opt = default_batch_options();
+  opt.graph_chunk = 0;  // no hipGraph: instantiating one allocates
+  const size_t need = batch_work_bytes(hs, count, opt);
+  if (need > kStaticWorkBytes)
+    return fail(ISING_ENOMEM,
+                "ising_multi_sweep_static: the batch needs %zu bytes of tables, more than the "
+                "%zu-byte static scratch",
+                need, kStaticWorkBytes);
+  const int device = hs[0]->device;
+  if (device < 0 || device >= 64) return fail(ISING_EINVAL, "ising_multi_sweep_static: device");
+  StaticScratch& S = static_scratch(device);
+  std::lock_guard<std::mutex> lock(S.m);
+  if (!S.ptr) {
+    int current = 0;
+    hipError_t e = hipGetDevice(&current);
+    if (e == hipSuccess && current != device) e = hipSetDevice(device);
+    void* p = nullptr;
+    if (e == hipSuccess) e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (current != device) (void)hipSetDevice(current);
+    if (e != hipSuccess || !p) return hip_fail(e, "ising_multi_sweep_static: scratch address");
+    S.ptr = p;
+  }
+  st = batch_sweeps(hs, count, n, nullptr, dev_EM, opt, S.ptr, kStaticWorkBytes, nullptr);
+  if (st != ISING_OK) return st;
+  for (int32_t i = 0; i < count; ++i) hs[i]->sweep += (uint64_t)n;
+  return ISING_OK;
+}
+
 extern "C" ising_status ising_multi_sweep_work_bytes(ising_t* const* hs, int32_t count,
                                                      size_t* bytes) {
   clear_error();

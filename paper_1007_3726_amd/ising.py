@@ -97,6 +97,7 @@ def lib():
         "ising_set_sweep": ([vp, u64], i32),
         "ising_get_info": ([vp, P(i64), P(i64), P(vp)], i32),
         "ising_multi_sweep_work_bytes": ([P(vp), i32, P(ctypes.c_size_t)], i32),
+        "ising_multi_sweep_static": ([P(vp), i32, i64, P(vp)], i32),
         "ising_multi_sweep": ([P(vp), i32, i64, P(vp), vp, ctypes.c_size_t], i32),
         "ising_multi_sweep_form": ([P(vp), i32, i64, P(vp), i32, i32, vp, ctypes.c_size_t],
                                    i32),
