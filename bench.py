@@ -76,6 +76,8 @@ def parse():
     p.add_argument("--no-batched", action="store_true",
                    help="skip the batched finite-size-scaling grid")
     p.add_argument("--batched-sweeps", type=int, default=workloads.FSS_SWEEPS)
+    p.add_argument("--no-fss-proof", action="store_true",
+                   help="skip the long small-lattice runs of the FSS proof of concept")
     p.add_argument("--workload", default="huge-T2",
                    choices=["large", "huge-T2", "huge-T3", "small", "paper-4096"],
                    help="plain workload: huge = 262144^2 (8 GiB, HBM-resident; T2 is the "
@@ -99,6 +101,8 @@ def parse():
     p.add_argument("--served-requests", type=int, default=2000,
                    help="requests of the 2000-request Poisson stream to serve (default: all, "
                         "about 160 s)")
+    p.add_argument("--served-capacity", type=int, default=300,
+                   help="requests of the stream queued at once to measure the server's capacity")
     p.add_argument("--served-arena-gib", type=float, default=1.0)
     p.add_argument("--served-quantum", type=int, default=400)
     p.add_argument("--plain-fifo-requests", type=int, default=200,
@@ -878,16 +882,17 @@ def main():
         print("bench: batched FSS grid (%d sweeps)" % args.batched_sweeps, file=sys.stderr,
               flush=True)
         result["batched"] = bench_batched(torch, ising, dev, args.batched_sweeps)
-        print("bench: FSS proof of concept (small lattices, long runs)", file=sys.stderr,
-              flush=True)
-        result["fss_proof"] = bench_fss_proof(torch, ising, dev)
+        if not args.no_fss_proof:
+            print("bench: FSS proof of concept (small lattices, long runs)", file=sys.stderr,
+                  flush=True)
+            result["fss_proof"] = bench_fss_proof(torch, ising, dev)
         torch.cuda.empty_cache()
     if not args.no_served:
         print("bench: served stream (%d requests)" % args.served_requests, file=sys.stderr,
               flush=True)
         result["served"] = bench_served(torch, ising, dev, args.served_requests,
                                         args.served_arena_gib, args.served_quantum,
-                                        args.plain_fifo_requests, value)
+                                        args.plain_fifo_requests, value, args.served_capacity)
     if not args.no_cpu_baseline:
         print("bench: CPU oracle baseline", file=sys.stderr, flush=True)
         result["cpu_baseline"] = cpu_baseline(w, args.cpu_sweeps, args.cpu_rows)
