@@ -1,14 +1,24 @@
-"""262144 x 262144 lattice (8 GiB packed, HBM-resident), hot start from seed 7.
+"""Lattices too large for the byte-per-spin oracle to hold.
 
-The full lattice is too large for the byte-per-spin oracle (68.7 GB), so
-parity is checked with light-cone windows: after n sweeps a site depends
-only on initial spins and uniforms within Manhattan distance 2n, and the
-oracle simulates a (w + 4n + 2)^2 patch keyed by global coordinates whose
-inner w x h window must equal the GPU's, bit for bit.  Windows sit at the
-corners (periodic wrap in both directions), edges and centre.  The per-sweep
-(E, M) series is checked for the invariants every configuration obeys and
-against an independent recount of the final state.
+262144 x 262144 (8 GiB packed, HBM-resident), hot start from seed 7, at
+T = 2.0 and 3.0 for the benchmark's 100 sweeps; 1048576^2 (2^33 words per
+colour plane) and 185368^2 (more than 2^32 Philox blocks per colour, L not a
+power of two).
+
+* The per-sweep int64 (E, M) is compared bit for bit with the oracle's
+  whole-lattice values (tests/golden/huge_em.txt, written by
+  tests/golden/make_huge_em.py from the oracle alone, which sums the
+  lattice band by band with light-cone margins): sweeps 1-10 at 262144^2,
+  1-4 at 185368^2 and sweep 1 at 1048576^2.
+* Spins are checked with light-cone windows: after n sweeps a site depends
+  only on initial spins and uniforms within Manhattan distance 2n, so the
+  oracle simulates a (w + 4n + 2)^2 patch keyed by global coordinates whose
+  inner w x h window must equal the GPU's, bit for bit.  Windows sit at the
+  corners (periodic wrap in both directions), edges and centre.
+* Every sweep's (E, M) obeys the invariants of any configuration, and the
+  last one equals an independent recount of the final state.
 """
+import os
 import sys
 
 import numpy as np
@@ -37,12 +47,41 @@ def _say(*a):
     sys.stdout.flush()
 
 
-@pytest.mark.parametrize("w,n", [(workloads.HUGE_T2, 100), (workloads.HUGE_T3, 30)])
-def test_huge_lattice_windows(I, w, n):
-    L = w.L
+def _golden():
+    """{(L, T, seed, stream_id, init): {sweep: (E, M)}} from the oracle's file."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "huge_em.txt")
+    out = {}
+    for line in open(path):
+        if line.startswith("#") or not line.strip():
+            continue
+        f = line.split()
+        key = (int(f[0]), float(f[1]), int(f[2]), int(f[3]), int(f[4]))
+        out.setdefault(key, {})[int(f[5])] = (int(f[6]), int(f[7]))
+    return out
+
+
+GOLDEN = _golden()
+
+
+def _check_golden(key, EM, required):
+    ref = GOLDEN.get(key)
+    if ref is None:
+        assert not required, "no oracle values for %r" % (key,)
+        _say("  (no oracle E/M for %r yet)" % (key,))
+        return
+    for k, (e, m) in sorted(ref.items()):
+        if k <= len(EM):
+            assert (int(EM[k - 1, 0]), int(EM[k - 1, 1])) == (e, m), "sweep %d of %r" % (k, key)
+    _say("  E/M of sweeps %s equal the oracle's" % sorted(ref))
+
+
+@pytest.mark.parametrize("w", [workloads.HUGE_T2, workloads.HUGE_T3])
+def test_huge_lattice_windows(I, w):
+    L, n = w.L, w.sweeps
     _say("case %s: %d sweeps" % (w.name, n))
     lat = I.Lattice(L, seed=w.seed, stream_id=w.stream_id, init=w.init, beta=1.0 / w.T)
     EM = lat.sweep_em(n).cpu().numpy()
+    _check_golden((L, w.T, w.seed, w.stream_id, w.init), EM, required=True)
     N = L * L
     assert np.all(EM[:, 0] % 4 == 0) and np.all((EM[:, 1] - N) % 2 == 0)
     assert np.all(np.abs(EM[:, 0]) <= 2 * N) and np.all(np.abs(EM[:, 1]) <= N)
@@ -63,6 +102,7 @@ def test_huge_lattice_windows(I, w, n):
 def _windows_and_invariants(I, L, T, seed, n, spots):
     lat = I.Lattice(L, seed=seed, stream_id=0, init=workloads.INIT_HOT, beta=1.0 / T)
     EM = lat.sweep_em(n).cpu().numpy()
+    _check_golden((L, T, seed, 0, workloads.INIT_HOT), EM, required=False)
     N = L * L
     assert np.all(EM[:, 0] % 4 == 0) and np.all((EM[:, 1] - N) % 2 == 0)
     assert np.all(np.abs(EM[:, 0]) <= 2 * N) and np.all(np.abs(EM[:, 1]) <= N)
