@@ -105,6 +105,21 @@ bool strip_form(const ising_lattice* h) {
 
 // Shape of the tiled half-sweep for this lattice; false when it does not
 // apply (L % 8 != 0, or Philox block indices that cross 2^32 inside a row).
+// Row groups per wave of the tile form for side L: the tuned value `want`
+// if it fits in LDS, else as many as keep >= 2048 tiles (8 per CU) and fit.
+int tile_rpw(int64_t L, int want) {
+  const int64_t W = words_per_row(L);
+  const bool wide = W >= kWideMinWords;
+  const int64_t TW = wide ? 64 : W, R = wide ? 1 : 64 / W, segs = wide ? (W + 63) / 64 : 1;
+  if (want > 0 && (4 * R * want + 2) * (TW + 2) <= kTileLdsMaxWords) return want;
+  for (int rpw = 4; rpw > 1; rpw >>= 1) {
+    const int64_t TR = 4 * R * rpw;
+    const int64_t tiles = ((L + TR - 1) / TR) * segs;
+    if (tiles >= 2048 && (TR + 2) * (TW + 2) <= kTileLdsMaxWords) return rpw;
+  }
+  return 1;
+}
+
 bool tile_args(const ising_lattice* h, TileArgs* out) {
   const int64_t L = h->L, W = h->g.W;
   if (L % 8 != 0) return false;
@@ -114,22 +129,7 @@ bool tile_args(const ising_lattice* h, TileArgs* out) {
   a.TW = wide ? 64 : (int32_t)W;
   a.R = wide ? 1 : (int32_t)(64 / W);
   a.segs = wide ? (int32_t)((W + 63) / 64) : 1;
-  const int want = h->tune.rpw;
-  // row groups per wave: the tuned value if it fits in LDS, else as many as
-  // keep >= 2048 tiles (8 per CU) and fit
-  a.RPW = 1;
-  if (want > 0 && (4 * (int64_t)a.R * want + 2) * (a.TW + 2) <= kTileLdsMaxWords) {
-    a.RPW = want;
-  } else {
-    for (int rpw = 4; rpw > 1; rpw >>= 1) {
-      const int64_t TR = 4 * (int64_t)a.R * rpw;
-      const int64_t tiles = ((L + TR - 1) / TR) * a.segs;
-      if (tiles >= 2048 && (TR + 2) * (a.TW + 2) <= kTileLdsMaxWords) {
-        a.RPW = rpw;
-        break;
-      }
-    }
-  }
+  a.RPW = tile_rpw(L, h->tune.rpw);
   const int64_t TR = 4 * (int64_t)a.R * a.RPW;
   a.tiles = ((L + TR - 1) / TR) * a.segs;
   if ((TR + 2) * (a.TW + 2) > kTileLdsMaxWords) return false;

@@ -27,6 +27,9 @@ struct Tuning {
 // Shape for a lattice of side L: the autotuner's entry for L's size class
 // if one is installed, else the defaults.
 Tuning default_tuning(int64_t L);
+// Row groups per wave the tile form uses for side L given the tuned value
+// (0: the size rule).
+int tile_rpw(int64_t L, int want);
 
 ising_status fail(ising_status code, const char* fmt, ...);
 ising_status hip_fail(hipError_t e, const char* what);

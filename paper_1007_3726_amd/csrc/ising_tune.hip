@@ -195,7 +195,8 @@ ising_status ising_tuning_lookup(int64_t L, ising_tuning* out) {
       if (L >= e.L_min && L <= e.L_max) r = e;
   }
   r.form = t.form;
-  r.rpw = t.rpw;
+  // the tile form's size rule (rpw 0) resolved to the value it uses
+  r.rpw = (t.form == ISING_FORM_TILE && L % 8 == 0) ? tile_rpw(L, t.rpw) : t.rpw;
   r.max_blocks = t.max_blocks;
   r.reserved = 0;
   r.small_lds_bytes = t.small_lds_bytes;

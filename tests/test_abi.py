@@ -101,6 +101,12 @@ def test_tuning_table_roundtrip(L):
     assert ising.tuning_lookup(64)["small_lds_bytes"] >= 2 * 64 * 8
     assert ising.tuning_lookup(4096)["form"] == ising.ISING_FORM_TILE
     assert ising.tuning_lookup(16384)["form"] == ising.ISING_FORM_TILE
+    # the size rule resolved: as many row groups per wave (4, 2) as keep
+    # >= 2048 tiles of 4 x R x rpw rows x 64-word segments
+    assert ising.tuning_lookup(16384)["rpw"] == 4    # 1024 x 2 tiles of 16 rows
+    assert ising.tuning_lookup(262144)["rpw"] == 4
+    assert ising.tuning_lookup(8192)["rpw"] == 1     # 1024 tiles at rpw 2: too few
+    assert ising.tuning_lookup(1024)["rpw"] == 1     # too few tiles for 2
     ising.tuning_set([e2])
     assert ising.tuning_lookup(9000)["rpw"] == 4 and ising.tuning_lookup(9000)["L_min"] == 8192
     ising.tuning_clear()
