@@ -527,14 +527,10 @@ typedef struct {
  * budget, caller-owned until ising_server_destroy).  The last 1/32 of the
  * arena (at least 4 KiB) holds the batched task tables; the rest holds the
  * lattices and their per-sweep series.  Requests are admitted in FIFO order
- * whenever their lattice, series and share of the table region fit
- * (continuous batching).  Each step runs one quantum of up to
- * quantum_sweeps sweeps, in fused launches, on every admitted lattice of
- * side > 256; lattices of side <= 256 run beside them on a second stream
- * the server creates, in batches of the packed persistent kernel that give
- * each about one quantum's time of sweeps.  Results do not depend on the
- * mix or the schedule: each lattice's uniforms are keyed by its own
- * (seed, stream_id, sweep).
+ * whenever their lattice, series and share of the table region fit;
+ * every quantum runs quantum_sweeps sweeps on all admitted lattices in
+ * fused launches (continuous batching).  Results do not depend on the mix:
+ * each lattice's uniforms are keyed by its own (seed, stream_id, sweep).
  * Errors: EINVAL (NULL or misaligned arena, arena under 8 KiB, quantum < 1).
  */
 ISING_API ising_status ising_server_create(void *dev_arena, size_t arena_bytes, void *hip_stream,

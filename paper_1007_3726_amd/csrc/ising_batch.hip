@@ -109,21 +109,16 @@ std::vector<std::vector<int>> pack_lpt(const std::vector<double>& cost, int bins
   return packs;
 }
 
-BatchPlan plan_batch(const std::vector<int64_t>& tiles, int cus, const PlanModel& m,
-                     int reserve_wgs, int max_packed_wgs) {
+BatchPlan plan_batch(const std::vector<int64_t>& tiles, int cus, const PlanModel& m) {
   BatchPlan p;
   const int count = (int)tiles.size();
   const int64_t total = std::accumulate(tiles.begin(), tiles.end(), (int64_t)0);
   // fused: two launches per sweep, each walking all tiles with the full grid
-  // (less the slots left to concurrent work: a static tile stride expects
-  // every workgroup of the grid to be resident at once)
-  const int64_t resident = std::max<int64_t>((int64_t)m.wg_per_cu * cus - reserve_wgs, cus);
-  p.fused_blocks = (int)std::min<int64_t>(std::max<int64_t>(total, 1), resident);
+  p.fused_blocks = (int)std::min<int64_t>(std::max<int64_t>(total, 1), (int64_t)m.wg_per_cu * cus);
   const double rounds = std::ceil((double)total / p.fused_blocks);
   p.fused_s = 2.0 * (m.launch_gap_s + rounds * m.tile_s_full);
   // packed: one workgroup per bin, all sweeps in one launch
-  int bins = std::min<int>(count, m.wg_per_cu * cus);
-  if (max_packed_wgs > 0) bins = std::min(bins, max_packed_wgs);
+  const int bins = std::min<int>(count, m.wg_per_cu * cus);
   std::vector<double> cost(count);
   for (int i = 0; i < count; ++i) cost[i] = (double)tiles[i];
   p.packs = pack_lpt(cost, bins);
@@ -270,7 +265,7 @@ static ising_status run_fused(ising_lattice* const* hs, const std::vector<int>& 
 static ising_status run_packed(ising_lattice* const* hs, const std::vector<int>& idx,
                                const std::vector<TileArgs>& targs, int64_t n, const int64_t* nsw,
                                int64_t* const* dev_EM, const BatchPlan& plan, char* work,
-                               size_t work_bytes, std::vector<char>* keep_image) {
+                               size_t work_bytes) {
   hipStream_t stream = hs[idx[0]]->stream;
   const int nl = (int)idx.size();
   std::vector<BatchLattice> lat(nl);
@@ -294,9 +289,7 @@ static ising_status run_packed(ising_lattice* const* hs, const std::vector<int>&
   if (pl.bytes > work_bytes)
     return fail(ISING_ENOMEM, "batched sweeps: work buffer of %zu bytes < %zu needed", work_bytes,
                 pl.bytes);
-  std::vector<char> local;
-  std::vector<char>& img = keep_image ? *keep_image : local;
-  img.assign(pl.bytes, 0);
+  std::vector<char> img(pl.bytes, 0);
   std::memcpy(img.data() + pl.off_lat, lat.data(), nl * sizeof(BatchLattice));
   std::memcpy(img.data() + pl.off_items, items.data(), items.size() * sizeof(BatchItem));
   std::memcpy(img.data() + pl.off_wgs, wgs.data(), wgs.size() * sizeof(BatchWG));
@@ -308,9 +301,8 @@ static ising_status run_packed(ising_lattice* const* hs, const std::vector<int>&
   a.wgs = (const BatchWG*)(work + pl.off_wgs);
   a.n = n;
   e = launch_batch(stream, a, (int)wgs.size());
-  // the host image must outlive the upload: wait before it goes, unless
-  // the caller keeps it
-  if (e == hipSuccess && !keep_image) e = hipStreamSynchronize(stream);
+  // the host image must outlive the upload: wait before it goes
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
   if (e != hipSuccess) return hip_fail(e, "batched sweeps: packed launch");
   return ISING_OK;
 }
@@ -399,7 +391,6 @@ ising_status batch_sweeps(ising_lattice* const* hs, int32_t count, int64_t n,
     if (st != ISING_OK) return st;
   }
   if (tiled.empty()) {
-    if (opt.keep_image) return ISING_OK;
     hipError_t e = hipStreamSynchronize(hs[0]->stream);
     return e == hipSuccess ? ISING_OK : hip_fail(e, "batched sweeps: synchronize");
   }
@@ -407,14 +398,12 @@ ising_status batch_sweeps(ising_lattice* const* hs, int32_t count, int64_t n,
   if (cus <= 0) return fail(ISING_EDEVICE, "batched sweeps: no device properties");
   std::vector<int64_t> tiles;
   for (int i : tiled) tiles.push_back(tile_cost(targs[i].tiles, targs[i].RPW));
-  const BatchPlan plan = plan_batch(tiles, cus, opt.model, opt.reserve_wgs, opt.max_packed_wgs);
+  const BatchPlan plan = plan_batch(tiles, cus, opt.model);
   bool packed = plan.packed;
   if (opt.force_form == 0) packed = false;
   if (opt.force_form == 1) packed = true;
   if (form_out) *form_out = packed ? 1 : 0;
-  if (packed)
-    return run_packed(hs, tiled, targs, n, nsw, dev_EM, plan, (char*)work, work_bytes,
-                      opt.keep_image);
+  if (packed) return run_packed(hs, tiled, targs, n, nsw, dev_EM, plan, (char*)work, work_bytes);
   // the fused grid walks actual tiles; size it for them
   int64_t ntiles = 0;
   for (int i : tiled) ntiles += targs[i].tiles;

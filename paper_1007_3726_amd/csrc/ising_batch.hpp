@@ -32,22 +32,11 @@ struct BatchOptions {
   PlanModel model;
   int force_form;   // -1: cost model, 0: fused, 1: packed
   int graph_chunk;  // sweeps per captured hipGraph chunk (0: no graph)
-  // packed form only: when set, the table image is kept here (it must
-  // outlive the asynchronous upload) and the call returns without waiting
-  // for the stream; the caller synchronises before it reuses the image or
-  // the work buffer
-  std::vector<char>* keep_image = nullptr;
-  // workgroup slots to leave to work running beside this call (fused form:
-  // the grid is that much smaller), and a cap on the packed form's
-  // workgroups (0: the model's resident count)
-  int reserve_wgs = 0;
-  int max_packed_wgs = 0;
 };
 
 PlanModel default_model();
 BatchOptions default_batch_options();
-BatchPlan plan_batch(const std::vector<int64_t>& tiles, int cus, const PlanModel& model,
-                     int reserve_wgs = 0, int max_packed_wgs = 0);
+BatchPlan plan_batch(const std::vector<int64_t>& tiles, int cus, const PlanModel& model);
 // Device bytes of the work buffer batch_sweeps needs for these handles
 // (0 when every lattice takes the plain path).
 size_t batch_work_bytes(ising_lattice* const* hs, int32_t count, const BatchOptions& opt);

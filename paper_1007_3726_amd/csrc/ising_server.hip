@@ -6,13 +6,12 @@
 //      their lattice and per-sweep (E, M) series fit in the free arena
 //      (first-fit allocator, 256-byte aligned); a request larger than the
 //      whole arena is rejected at submission;
-//   2. one batched call advances the chosen active lattices by up to
+//   2. one batched call advances every active lattice by up to
 //      quantum_sweeps sweeps (fewer for a request that has fewer left), all
-//      together in fused launches, with the task tables in a region
-//      reserved at the end of the arena (1/32 of it; every admitted lattice
-//      also reserves its share of that region, so the tables of any active
-//      set fit); small lattices run beside them in batches of the packed
-//      persistent kernel on a second stream (see "Scheduling" below);
+//      lattices together in fused launches or one packed launch, with the
+//      task tables in a region reserved at the end of the arena (1/32 of
+//      it; every admitted lattice also reserves its share of that region,
+//      so the tables of any active set fit);
 //   3. retirement: finished requests copy their series/spins to the
 //      caller's host buffers, get exact moment sums, a completion time, and
 //      free their arena space, so the next step can admit more.
@@ -118,20 +117,8 @@ struct ising_server {
   size_t arena_bytes;   // lattice and series space: [0, arena_bytes)
   char* table;          // task-table region: [arena_bytes, arena_bytes + table_bytes)
   size_t table_bytes;
-  // the fixed parts of both launch sets plus the active shares
-  size_t table_used = 2 * kBatchWorkFixed;
+  size_t table_used = kBatchWorkFixed;  // the fixed part plus the active shares
   hipStream_t stream;
-  hipStream_t side = nullptr;    // small lattices' persistent launches
-  hipEvent_t admitted_ev = nullptr;
-  hipEvent_t side_done = nullptr;
-  bool side_running = false;     // a batch of small lattices is in flight
-  std::vector<uint64_t> side_jobs;  // its tickets and sweeps
-  std::vector<int64_t> side_nsw;
-  size_t side_bytes = 0;         // its tables at the start of the table region
-  int side_wgs = 0;              // workgroups it holds (multiple of 8)
-  int cus = 0;                   // compute units of the device
-  std::vector<char> side_image;  // its table image (outlives the upload)
-  double quantum_s = 0.02;       // smoothed wall time of the large set's quanta
   int32_t quantum;
   Arena arena;
   uint64_t next_ticket = 1;
@@ -268,251 +255,72 @@ ising_status retire(ising_server* s, Job& j) {
   return ISING_OK;
 }
 
-// Scheduling (readings of this build; results never depend on them, since
-// every lattice's uniforms are keyed by its own seed, stream and sweep):
-//  * small lattices (side <= kSmallL, one workgroup each in the packed
-//    persistent kernel) run in batches on a second stream, concurrently
-//    with the rest and decoupled from its quanta: each batch gives every
-//    active small lattice as many sweeps as fit in about one large-set
-//    quantum (at least one), and the next batch starts when the host sees
-//    the previous one finished.  Under sweep-synchronous quanta a small
-//    lattice with many sweeps would otherwise wait for hundreds of quanta.
-//    A batch takes at most one workgroup per compute unit, and while one
-//    runs the fused grid of the large set is smaller by as many
-//    workgroups, so both stay resident together;
-//  * the other lattices all take up to Q sweeps per quantum in fused
-//    launches.
-constexpr int64_t kSmallL = 256;
-
-// Seconds per sweep of a small lattice alone on one workgroup: two colour
-// steps of its tiles at the measured one-workgroup tile time.
-double small_sweep_s(int64_t L) {
-  const int64_t W = words_per_row(L);
-  const int64_t R = W >= kWideMinWords ? 1 : std::max<int64_t>(1, 64 / W);
-  const int64_t tiles = (L + 4 * R - 1) / (4 * R) * (W >= kWideMinWords ? (W + 63) / 64 : 1);
-  return 2.0 * (double)tiles * default_model().tile_s_alone;
-}
-
-bool is_small(const Job& j) { return j.req.L <= kSmallL; }
-
-// Launch one batch of every active small lattice on the side stream
-// (asynchronous); its tables take the start of the table region.
-ising_status launch_side(ising_server* s, double budget) {
-  if (!s->side) {
-    hipError_t e = hipStreamCreateWithFlags(&s->side, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&s->admitted_ev, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&s->side_done, hipEventDisableTiming);
-    if (e != hipSuccess) return hip_fail(e, "server: side stream");
-  }
-  if (s->cus == 0) {
-    int dev = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e == hipSuccess)
-      e = hipDeviceGetAttribute(&s->cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (e != hipSuccess || s->cus < 1) return hip_fail(e, "server: compute units");
-  }
-  std::vector<ising_lattice*> hs;
-  std::vector<int64_t> nsw;
-  std::vector<int64_t*> ems;
-  s->side_jobs.clear();
-  s->side_nsw.clear();
-  int64_t nsmall = 0;
-  for (uint64_t t : s->active) nsmall += is_small(s->jobs.at(t)) ? 1 : 0;
-  // at most one workgroup per compute unit: lattices share workgroups
-  // (one after another) when there are more, so each takes its share
-  const int64_t per_wg = (nsmall + s->cus - 1) / s->cus;
-  budget /= (double)std::max<int64_t>(per_wg, 1);
-  int64_t n = 0;
-  for (uint64_t t : s->active) {
-    Job& j = s->jobs.at(t);
-    if (!is_small(j)) continue;
-    int64_t take = std::max<int64_t>((int64_t)(budget / small_sweep_s(j.req.L)), 1);
-    take = std::min<int64_t>(take, j.req.n_sweeps - j.done);
-    hs.push_back(j.h);
-    nsw.push_back(take);
-    ems.push_back(j.dev_series + 2 * j.done);
-    s->side_jobs.push_back(t);
-    s->side_nsw.push_back(take);
-    n = std::max(n, take);
-  }
-  if (hs.empty()) return ISING_OK;
-  // the side stream starts after everything enqueued so far on the main
-  // stream (the new lattices' initial states)
-  hipError_t e = hipEventRecord(s->admitted_ev, s->stream);
-  if (e == hipSuccess) e = hipStreamWaitEvent(s->side, s->admitted_ev, 0);
-  if (e != hipSuccess) return hip_fail(e, "server: side stream order");
+// One batched call over the active set; each lattice takes up to Q sweeps.
+ising_status run_quantum(ising_server* s, std::vector<ising_lattice*>& hs,
+                         std::vector<int64_t>& nsw, std::vector<int64_t*>& ems, int64_t n) {
   BatchOptions opt = default_batch_options();
-  opt.force_form = 1;
-  opt.keep_image = &s->side_image;
-  opt.max_packed_wgs = s->cus;
-  // the workgroups the batch holds, rounded up to whole XCD groups of 8
-  s->side_wgs = (int)((std::min<int64_t>((int64_t)hs.size(), s->cus) + 7) / 8 * 8);
-  s->side_bytes = (batch_work_bytes(hs.data(), (int32_t)hs.size(), opt) + 255) & ~(size_t)255;
-  for (ising_lattice* h : hs) h->stream = s->side;
   ising_status st = batch_sweeps(hs.data(), (int32_t)hs.size(), n, nsw.data(), ems.data(), opt,
-                                 s->table, s->side_bytes, nullptr);
-  for (ising_lattice* h : hs) h->stream = s->stream;
-  if (st == ISING_OK) {
-    e = hipEventRecord(s->side_done, s->side);
-    if (e != hipSuccess) st = hip_fail(e, "server: side event");
-  }
-  s->side_running = true;  // even on failure: wait for whatever was enqueued
-  return st;
-}
-
-// The side batch has finished (or is waited for): count its sweeps and
-// retire the small lattices that are done.
-ising_status finish_side(ising_server* s, bool wait) {
-  if (!s->side_running) return ISING_OK;
-  hipError_t e = wait ? hipEventSynchronize(s->side_done) : hipEventQuery(s->side_done);
-  if (e == hipErrorNotReady) return ISING_AGAIN;
-  if (e != hipSuccess) return hip_fail(e, "server: small lattices");
-  s->side_running = false;
-  s->side_bytes = 0;
-  s->side_wgs = 0;
-  for (size_t i = 0; i < s->side_jobs.size(); ++i) {
-    Job& j = s->jobs.at(s->side_jobs[i]);
-    j.h->sweep += (uint64_t)s->side_nsw[i];
-    j.done += s->side_nsw[i];
-  }
-  std::vector<uint64_t> still;
-  for (uint64_t t : s->active) {
-    Job& j = s->jobs.at(t);
-    if (is_small(j) && j.done >= j.req.n_sweeps) {
-      ising_status st = retire(s, j);
-      if (st != ISING_OK) return st;
-    } else {
-      still.push_back(t);
-    }
-  }
-  s->active.swap(still);
-  return ISING_OK;
-}
-
-// One quantum of every large lattice (synchronous); returns their tickets
-// and sweeps.
-ising_status run_large(ising_server* s, std::vector<uint64_t>& ran, std::vector<int64_t>& took) {
-  std::vector<ising_lattice*> hs;
-  std::vector<int64_t> nsw;
-  std::vector<int64_t*> ems;
-  int64_t n = 0;
-  for (uint64_t t : s->active) {
-    Job& j = s->jobs.at(t);
-    if (is_small(j)) continue;
-    const int64_t take = std::min<int64_t>(s->quantum, j.req.n_sweeps - j.done);
-    hs.push_back(j.h);
-    nsw.push_back(take);
-    ems.push_back(j.dev_series + 2 * j.done);
-    ran.push_back(t);
-    took.push_back(take);
-    n = std::max(n, take);
-  }
-  if (hs.empty()) return ISING_OK;
-  const double t0 = now_s();
-  BatchOptions opt = default_batch_options();
-  if (s->side_running) opt.reserve_wgs = s->side_wgs;
-  // the side batch's tables sit at the start of the region
-  ising_status st = batch_sweeps(hs.data(), (int32_t)hs.size(), n, nsw.data(), ems.data(), opt,
-                                 s->table + s->side_bytes, s->table_bytes - s->side_bytes,
-                                 nullptr);
+                                 s->table, s->table_bytes, nullptr);
   if (st != ISING_OK) return st;
   hipError_t e = hipStreamSynchronize(s->stream);
-  if (e != hipSuccess) return hip_fail(e, "server: quantum");
-  s->quantum_s = 0.7 * s->quantum_s + 0.3 * std::max(now_s() - t0, 1e-3);
-  return ISING_OK;
-}
-
-ising_status commit_large(ising_server* s, const std::vector<uint64_t>& ran,
-                          const std::vector<int64_t>& took) {
-  for (size_t i = 0; i < ran.size(); ++i) {
-    Job& j = s->jobs.at(ran[i]);
-    j.h->sweep += (uint64_t)took[i];
-    j.done += took[i];
-  }
-  std::vector<uint64_t> still;
-  for (uint64_t t : s->active) {
-    Job& j = s->jobs.at(t);
-    if (!is_small(j) && j.done >= j.req.n_sweeps) {
-      ising_status st = retire(s, j);
-      if (st != ISING_OK) return st;
-    } else {
-      still.push_back(t);
-    }
-  }
-  s->active.swap(still);
-  return ISING_OK;
-}
-
-bool any_large(const ising_server* s) {
-  for (uint64_t t : s->active)
-    if (!is_small(s->jobs.at(t))) return true;
-  return false;
+  return e == hipSuccess ? ISING_OK : hip_fail(e, "server: quantum");
 }
 
 ising_status step(ising_server* s) {
   ising_status st = admit(s);
   if (st != ISING_OK) return st;
-  if (s->active.empty() && !s->side_running) return s->queue.empty() ? ISING_OK : ISING_AGAIN;
+  if (s->active.empty()) return s->queue.empty() ? ISING_OK : ISING_AGAIN;
+  std::vector<ising_lattice*> hs;
+  std::vector<int64_t> nsw;
+  std::vector<int64_t*> ems;
+  int64_t n = 0;
+  for (uint64_t t : s->active) {
+    Job& j = s->jobs.at(t);
+    const int64_t take = std::min<int64_t>(s->quantum, j.req.n_sweeps - j.done);
+    hs.push_back(j.h);
+    nsw.push_back(take);
+    ems.push_back(j.dev_series + 2 * j.done);
+    n = std::max(n, take);
+  }
   const int64_t q = s->quanta++;
   if (s->faults.count(q)) {
-    // finish the side batch, then snapshot every active lattice, run one
-    // round of both sets, declare it failed, restore, and run it again
-    st = finish_side(s, true);
-    if (st != ISING_OK) return st;
-    std::vector<ising_lattice*> all;
-    for (uint64_t t : s->active) all.push_back(s->jobs.at(t).h);
-    std::vector<std::vector<char>> snap(all.size());
-    for (size_t i = 0; i < all.size(); ++i) {
-      snap[i].resize(2 * (size_t)all[i]->plane_words * sizeof(uint64_t));
-      hipError_t e = hipMemcpyAsync(snap[i].data(), all[i]->planes, snap[i].size(),
+    // snapshot, run, declare the quantum failed, restore, run again
+    std::vector<std::vector<char>> snap(hs.size());
+    for (size_t i = 0; i < hs.size(); ++i) {
+      snap[i].resize(2 * (size_t)hs[i]->plane_words * sizeof(uint64_t));
+      hipError_t e = hipMemcpyAsync(snap[i].data(), hs[i]->planes, snap[i].size(),
                                     hipMemcpyDeviceToHost, s->stream);
       if (e != hipSuccess) return hip_fail(e, "server: snapshot");
     }
-    hipError_t e = hipStreamSynchronize(s->stream);
-    if (e != hipSuccess) return hip_fail(e, "server: snapshot");
-    st = launch_side(s, s->quantum_s);
-    std::vector<uint64_t> ran;
-    std::vector<int64_t> took;
-    if (st == ISING_OK) st = run_large(s, ran, took);
-    if (s->side_running) {
-      e = hipEventSynchronize(s->side_done);
-      s->side_running = false;
-      s->side_bytes = 0;
-      s->side_wgs = 0;
-      if (st == ISING_OK && e != hipSuccess) st = hip_fail(e, "server: small lattices");
-    }
+    st = run_quantum(s, hs, nsw, ems, n);
     if (st != ISING_OK) return st;
-    for (size_t i = 0; i < all.size(); ++i) {
-      e = hipMemcpyAsync(all[i]->planes, snap[i].data(), snap[i].size(), hipMemcpyHostToDevice,
-                         s->stream);
+    for (size_t i = 0; i < hs.size(); ++i) {
+      hipError_t e = hipMemcpyAsync(hs[i]->planes, snap[i].data(), snap[i].size(),
+                                    hipMemcpyHostToDevice, s->stream);
       if (e != hipSuccess) return hip_fail(e, "server: restore");
     }
     // the restore reads host memory that ends with this block
-    e = hipStreamSynchronize(s->stream);
+    hipError_t e = hipStreamSynchronize(s->stream);
     if (e != hipSuccess) return hip_fail(e, "server: restore");
     s->faults.erase(q);
     ++s->recovered;
   }
-  // small lattices: collect a finished batch, start the next one
-  st = finish_side(s, false);
-  if (st != ISING_OK && st != ISING_AGAIN) return st;
-  if (!s->side_running) {
-    st = launch_side(s, any_large(s) ? s->quantum_s : std::max(s->quantum_s, 0.005));
-    if (st != ISING_OK) return st;
-  }
-  // large lattices: one quantum; with none, wait for the side batch
-  std::vector<uint64_t> ran;
-  std::vector<int64_t> took;
-  st = run_large(s, ran, took);
+  st = run_quantum(s, hs, nsw, ems, n);
   if (st != ISING_OK) return st;
-  if (ran.empty()) {
-    st = finish_side(s, true);
-    if (st != ISING_OK) return st;
-  } else {
-    st = commit_large(s, ran, took);
-    if (st != ISING_OK) return st;
+  std::vector<uint64_t> still;
+  for (size_t i = 0; i < s->active.size(); ++i) {
+    Job& j = s->jobs.at(s->active[i]);
+    j.h->sweep += (uint64_t)nsw[i];
+    j.done += nsw[i];
+    if (j.done >= j.req.n_sweeps) {
+      st = retire(s, j);
+      if (st != ISING_OK) return st;
+    } else {
+      still.push_back(j.ticket);
+    }
   }
-  return (s->active.empty() && s->queue.empty() && !s->side_running) ? ISING_OK : ISING_AGAIN;
+  s->active.swap(still);
+  return (s->active.empty() && s->queue.empty()) ? ISING_OK : ISING_AGAIN;
 }
 
 }  // namespace
@@ -645,15 +453,8 @@ ising_status ising_server_stats(const ising_server_t* s, int64_t out[6]) {
 ising_status ising_server_destroy(ising_server_t* s) {
   clear_error();
   if (!s) return ISING_OK;
-  // a batch of small lattices may still be running on the side stream
-  if (s->side) {
-    (void)hipStreamSynchronize(s->side);
-    (void)hipStreamDestroy(s->side);
-  }
   for (auto& kv : s->jobs)
     if (kv.second.h) ising_destroy(kv.second.h);
-  if (s->admitted_ev) (void)hipEventDestroy(s->admitted_ev);
-  if (s->side_done) (void)hipEventDestroy(s->side_done);
   delete s;
   return ISING_OK;
 }
