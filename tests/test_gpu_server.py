@@ -168,3 +168,28 @@ def test_served_stream_requests_against_the_oracle(I, quantum):
             want = oracle.window(L, r["beta"], r["seed"], r["stream_id"], r["init"], 0, n, x0, y0,
                                  40, 12)
             assert np.array_equal(got["spins"][np.ix_(ys, xs)], want), (r, x0, y0)
+
+
+def test_schedule_never_changes_results(I):
+    """Five 8192^2 lattices with different sweep counts in quanta of 8
+    sweeps (they leave the fused launches at different quanta, and the
+    lattices left take the plain path or fused launches by the cost model),
+    beside small lattices: every result equals the same request alone on
+    the plain path."""
+    reqs = []
+    for i, (L, n) in enumerate([(8192, 30), (8192, 11), (8192, 47), (8192, 20), (8192, 36),
+                                (64, 900), (256, 300), (32, 5000), (128, 70)]):
+        reqs.append({"L": L, "beta": 1.0 / (2.0 + 0.1 * i), "seed": 77 + i, "stream_id": i,
+                     "init": workloads.INIT_HOT, "n_sweeps": n, "n_discard": 0,
+                     "record_series": True, "return_spins": L <= 256})
+    _say("case schedule: five 8192^2 and four small lattices, quantum 8")
+    res, stats = _run(I, reqs, 1 << 30, 8)
+    assert stats["done"] == len(reqs)
+    for r, got in zip(reqs, res):
+        lat = I.Lattice(r["L"], seed=r["seed"], stream_id=r["stream_id"], init=r["init"],
+                        beta=r["beta"])
+        em = lat.sweep_em(r["n_sweeps"]).cpu().numpy()
+        assert np.array_equal(got["series"], em), r
+        if r["L"] <= 256:
+            assert np.array_equal(got["spins"], lat.get_spins()), r
+        del lat
