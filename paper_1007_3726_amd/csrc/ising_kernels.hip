@@ -536,10 +536,11 @@ __device__ __forceinline__ void process_tile_direct(const TileArgs& a, const Til
   for (int j = 0; j < RPW; ++j) {
     int64_t y;
     int32_t w;
+    uint32_t iu = 0;  // flat shapes: the word's index in its plane
     if (FLAT) {
       const int64_t i = ((tidx * 4 + wave) * RPW + j) * 64 + (threadIdx.x & 63);
       if (i >= a.plane_words) continue;
-      const uint32_t iu = (uint32_t)i;  // plane_words < 2^32 for flat shapes
+      iu = (uint32_t)i;  // plane_words < 2^32 for flat shapes
       if (W == 1) {  // floor(2^32 / 1) + 1 does not fit 32 bits
         y = iu;
         w = 0;
@@ -559,20 +560,37 @@ __device__ __forceinline__ void process_tile_direct(const TileArgs& a, const Til
       w = w0 + tl.w_l;
       if (!(tl.lane_ok && y < g.L && w < W)) continue;
     }
-    const int64_t ym = y == 0 ? g.L - 1 : y - 1;
-    const int64_t yp = y == g.L - 1 ? 0 : y + 1;
     // horizontal partner: left (site k-1) when (y + colour) is even, else right
     const bool left = ((y + colour) & 1) == 0;
     const int32_t ws = left ? (w > 0 ? w - 1 : (int32_t)W - 1) : (w < W - 1 ? w + 1 : 0);
-    const uint64_t s = self[y * W + w];
-    const uint64_t n0 = other[y * W + w];
-    const uint64_t n2 = other[ym * W + w];
-    const uint64_t n3 = other[yp * W + w];
-    const uint64_t sd = other[y * W + ws];
+    // word offsets in a plane of the word, its row neighbours (periodic) and
+    // its horizontal partner; flat shapes have planes of < 2^32 words, so
+    // they derive all four from the word's own index in 32-bit arithmetic
+    uint64_t off, off_m, off_p, off_s;
+    if (FLAT) {
+      const uint32_t W32 = (uint32_t)W;
+      const uint32_t wrap = (uint32_t)(a.plane_words - W);  // offset of the last row
+      off = iu;
+      off_m = y == 0 ? iu + wrap : iu - W32;
+      off_p = y == g.L - 1 ? iu - wrap : iu + W32;
+      off_s = iu + (uint32_t)(ws - w);
+    } else {
+      const int64_t ym = y == 0 ? g.L - 1 : y - 1;
+      const int64_t yp = y == g.L - 1 ? 0 : y + 1;
+      off = (uint64_t)(y * W + w);
+      off_m = (uint64_t)(ym * W + w);
+      off_p = (uint64_t)(yp * W + w);
+      off_s = (uint64_t)(y * W + ws);
+    }
+    const uint64_t s = self[off];
+    const uint64_t n0 = other[off];
+    const uint64_t n2 = other[off_m];
+    const uint64_t n3 = other[off_p];
+    const uint64_t sd = other[off_s];
     uint64_t r4, r8;
     if (LCG) {
       // this word's generator: thread (colour L + y) W + w
-      uint32_t* xs = a.lcg + ((int64_t)colour * g.L + y) * W + w;
+      uint32_t* xs = a.lcg + (colour ? a.plane_words : 0) + off;
       uint32_t z = *xs + a.l4d;
       masks_lcg(z, a.lc, a.le, a.l4m, a.l8m, r4, r8);
       *xs = z - a.l4d;
@@ -606,7 +624,7 @@ __device__ __forceinline__ void process_tile_direct(const TileArgs& a, const Til
     const uint64_t s_new = s ^ (flip_mask(s, n, r4, r8) & valid);
     // write-through at device scope (sc1): the XCD L2s then hold no dirty
     // lattice lines for the write-back at the end of the launch
-    __hip_atomic_store(&self[y * W + w], s_new, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&self[off], s_new, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (colour == 1 && em) count_word(s_new, n, valid, anti, up);
   }
 }
