@@ -85,6 +85,9 @@ def parse():
                         "0.99 T_c")
     p.add_argument("--no-configs", action="store_true",
                    help="skip the other plain configurations")
+    p.add_argument("--side-workload", default="large", choices=["large", "headline"],
+                   help="lattice of the LCG, pattern-pool and multi-spin CPU legs: 16384^2 "
+                        "(default) or the headline workload")
     p.add_argument("--no-served", action="store_true", help="skip the served request stream")
     p.add_argument("--no-cpu-msc", action="store_true",
                    help="skip the multi-spin-coded CPU baseline")
@@ -853,7 +856,7 @@ def main():
     }
     if not args.no_configs:
         result["configs"] = bench_configs(torch, ising, dev, stream, w)
-    side = workloads.LARGE if w.L > 65536 else w
+    side = workloads.LARGE if (w.L > 65536 and args.side_workload == "large") else w
     side_steps = max(1, min(args.steps, 3))
     if not args.no_lcg:
         print("bench: %s with the paper's LCG random numbers" % side.name, file=sys.stderr,
