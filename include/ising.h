@@ -541,8 +541,13 @@ ISING_API ising_status ising_server_create(void *dev_arena, size_t arena_bytes, 
 ISING_API ising_status ising_batch_submit(ising_server_t *s, const ising_request *reqs, int32_t n,
                                 uint64_t *tickets_out);
 
-/* Advance the server by one quantum (admit, run, retire).  Returns AGAIN
- * while work remains, OK when idle. */
+/* Advance the server by one quantum: wait for the quantum in flight, start
+ * copying the series of the requests it finished, admit, enqueue the next
+ * quantum on the stream without waiting for it, then finish the finished
+ * requests' results on the host (so the GPU runs while the host retires).
+ * Returns AGAIN while work remains or a quantum is in flight, OK when idle
+ * (nothing queued, active or in flight).  The server creates one pinned
+ * host staging buffer for the series copies. */
 ISING_API ising_status ising_server_step(ising_server_t *s);
 
 /* Result of a ticket: OK (done, *out filled, ticket released), AGAIN

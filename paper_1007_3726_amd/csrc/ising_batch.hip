@@ -183,13 +183,16 @@ static ising_status run_fused(ising_lattice* const* hs, const std::vector<int>& 
                 fl.bytes);
   // the image covers the sweep counter (zero) and the tables; the partials
   // are written before they are read
-  std::vector<char> img(fl.off_part, 0);
+  const bool async = opt.keep_image != nullptr && opt.graph_chunk == 0;
+  std::vector<char> local;
+  std::vector<char>& img = async ? *opt.keep_image : local;
+  img.assign(fl.off_part, 0);
   std::memcpy(img.data() + fl.off_lat, lat.data(), nl * sizeof(FusedLattice));
   std::memcpy(img.data() + fl.off_tiles, tiles.data(), ntiles * sizeof(FusedTile));
   hipError_t e = hipMemcpyAsync(work, img.data(), img.size(), hipMemcpyHostToDevice, stream);
   if (e != hipSuccess) return hip_fail(e, "batched sweeps: table upload");
-  // the host image ends with this call
-  e = hipStreamSynchronize(stream);
+  // a local image ends with this call: wait for its upload
+  if (!async) e = hipStreamSynchronize(stream);
   if (e != hipSuccess) return hip_fail(e, "batched sweeps: table upload");
 
   FusedArgs f;
@@ -257,6 +260,7 @@ static ising_status run_fused(ising_lattice* const* hs, const std::vector<int>& 
     e = launch_fused_finalize(stream, f, std::min(nl, 1024));
     if (e != hipSuccess) return hip_fail(e, "batched sweeps: finalize launch");
   }
+  if (async) return ISING_OK;
   e = hipStreamSynchronize(stream);
   if (e != hipSuccess) return hip_fail(e, "batched sweeps: synchronize");
   return ISING_OK;
@@ -265,7 +269,7 @@ static ising_status run_fused(ising_lattice* const* hs, const std::vector<int>& 
 static ising_status run_packed(ising_lattice* const* hs, const std::vector<int>& idx,
                                const std::vector<TileArgs>& targs, int64_t n, const int64_t* nsw,
                                int64_t* const* dev_EM, const BatchPlan& plan, char* work,
-                               size_t work_bytes) {
+                               size_t work_bytes, std::vector<char>* keep_image) {
   hipStream_t stream = hs[idx[0]]->stream;
   const int nl = (int)idx.size();
   std::vector<BatchLattice> lat(nl);
@@ -289,7 +293,9 @@ static ising_status run_packed(ising_lattice* const* hs, const std::vector<int>&
   if (pl.bytes > work_bytes)
     return fail(ISING_ENOMEM, "batched sweeps: work buffer of %zu bytes < %zu needed", work_bytes,
                 pl.bytes);
-  std::vector<char> img(pl.bytes, 0);
+  std::vector<char> local;
+  std::vector<char>& img = keep_image ? *keep_image : local;
+  img.assign(pl.bytes, 0);
   std::memcpy(img.data() + pl.off_lat, lat.data(), nl * sizeof(BatchLattice));
   std::memcpy(img.data() + pl.off_items, items.data(), items.size() * sizeof(BatchItem));
   std::memcpy(img.data() + pl.off_wgs, wgs.data(), wgs.size() * sizeof(BatchWG));
@@ -301,8 +307,9 @@ static ising_status run_packed(ising_lattice* const* hs, const std::vector<int>&
   a.wgs = (const BatchWG*)(work + pl.off_wgs);
   a.n = n;
   e = launch_batch(stream, a, (int)wgs.size());
-  // the host image must outlive the upload: wait before it goes
-  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  // the host image must outlive the upload: wait before it goes, unless the
+  // caller keeps it
+  if (e == hipSuccess && !keep_image) e = hipStreamSynchronize(stream);
   if (e != hipSuccess) return hip_fail(e, "batched sweeps: packed launch");
   return ISING_OK;
 }
@@ -391,6 +398,7 @@ ising_status batch_sweeps(ising_lattice* const* hs, int32_t count, int64_t n,
     if (st != ISING_OK) return st;
   }
   if (tiled.empty()) {
+    if (opt.keep_image) return ISING_OK;
     hipError_t e = hipStreamSynchronize(hs[0]->stream);
     return e == hipSuccess ? ISING_OK : hip_fail(e, "batched sweeps: synchronize");
   }
@@ -403,7 +411,9 @@ ising_status batch_sweeps(ising_lattice* const* hs, int32_t count, int64_t n,
   if (opt.force_form == 0) packed = false;
   if (opt.force_form == 1) packed = true;
   if (form_out) *form_out = packed ? 1 : 0;
-  if (packed) return run_packed(hs, tiled, targs, n, nsw, dev_EM, plan, (char*)work, work_bytes);
+  if (packed)
+    return run_packed(hs, tiled, targs, n, nsw, dev_EM, plan, (char*)work, work_bytes,
+                      opt.keep_image);
   // the fused grid walks actual tiles; size it for them
   int64_t ntiles = 0;
   for (int i : tiled) ntiles += targs[i].tiles;

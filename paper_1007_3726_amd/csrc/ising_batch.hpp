@@ -32,6 +32,11 @@ struct BatchOptions {
   PlanModel model;
   int force_form;   // -1: cost model, 0: fused, 1: packed
   int graph_chunk;  // sweeps per captured hipGraph chunk (0: no graph)
+  // when set (with graph_chunk 0): the table image is kept here, since it
+  // must outlive its asynchronous upload, and the call returns without
+  // waiting for the stream; the caller synchronises before it reuses the
+  // image or the work buffer
+  std::vector<char>* keep_image = nullptr;
 };
 
 PlanModel default_model();

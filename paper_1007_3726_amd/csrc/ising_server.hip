@@ -127,6 +127,17 @@ struct ising_server {
   std::vector<uint64_t> active;
   std::set<int64_t> faults;
   int64_t quanta = 0, admitted = 0, finished = 0, peak = 0, recovered = 0;
+  // the quantum in flight: its tickets and sweeps, and its table image
+  bool inflight = false;
+  std::vector<uint64_t> ran;
+  std::vector<int64_t> took;
+  std::vector<char> image;
+  // retirement in progress: tickets whose series are being copied to the
+  // pinned staging buffer (offsets in int64 words), and the copies' event
+  std::vector<std::pair<uint64_t, size_t>> leaving;
+  int64_t* staging = nullptr;
+  size_t staging_words = 0;
+  hipEvent_t copied = nullptr;
   explicit ising_server(size_t bytes) : arena(bytes) {}
 };
 
@@ -228,51 +239,108 @@ void moments(const int64_t* series, int64_t n, int64_t discard, ising_result* r)
   exact_moments(series, n, discard, &r->sum_M2, &r->sum_M4, &r->n_kept);
 }
 
-ising_status retire(ising_server* s, Job& j) {
-  std::vector<int64_t> series((size_t)j.req.n_sweeps * 2);
-  hipError_t e = hipMemcpyAsync(series.data(), j.dev_series, series.size() * sizeof(int64_t),
-                                hipMemcpyDeviceToHost, s->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
-  if (e != hipSuccess) return hip_fail(e, "server: series copy");
-  if ((j.req.flags & ISING_REQ_RECORD_SERIES) && j.req.EM_series)
-    std::memcpy(j.req.EM_series, series.data(), series.size() * sizeof(int64_t));
-  if ((j.req.flags & ISING_REQ_RETURN_SPINS) && j.req.spins_out) {
-    ising_status st = ising_get_spins(j.h, j.req.spins_out);
-    if (st != ISING_OK) return st;
+// Retirement, first half: the finished requests' series are copied to the
+// pinned staging buffer on the stream (spins, if asked for, synchronously),
+// and their arena space is released at once: anything that reuses it is
+// enqueued later on the same stream.
+ising_status begin_retire(ising_server* s, const std::vector<uint64_t>& done) {
+  s->leaving.clear();
+  if (done.empty()) return ISING_OK;
+  size_t words = 0;
+  for (uint64_t t : done) words += 2 * (size_t)s->jobs.at(t).req.n_sweeps;
+  if (words > s->staging_words) {
+    if (s->staging) (void)hipHostFree(s->staging);
+    s->staging = nullptr;
+    s->staging_words = 0;
+    const size_t want = std::max<size_t>(words, size_t(1) << 20);
+    hipError_t e = hipHostMalloc((void**)&s->staging, want * sizeof(int64_t), 0);
+    if (e != hipSuccess) return hip_fail(e, "server: staging buffer");
+    s->staging_words = want;
   }
-  j.res.E_final = series[series.size() - 2];
-  j.res.M_final = series[series.size() - 1];
-  j.res.sweeps_done = (uint64_t)j.done;
-  moments(series.data(), j.req.n_sweeps, j.req.n_discard, &j.res);
-  j.res.status = ISING_OK;
-  j.res.t_done = now_s();
-  ising_destroy(j.h);
-  j.h = nullptr;
-  s->arena.release(j.off, j.bytes);
-  s->table_used -= j.share;
-  j.state = State::Done;
-  ++s->finished;
+  if (!s->copied) {
+    hipError_t e = hipEventCreateWithFlags(&s->copied, hipEventDisableTiming);
+    if (e != hipSuccess) return hip_fail(e, "server: event");
+  }
+  size_t off = 0;
+  for (uint64_t t : done) {
+    Job& j = s->jobs.at(t);
+    const size_t n = 2 * (size_t)j.req.n_sweeps;
+    hipError_t e = hipMemcpyAsync(s->staging + off, j.dev_series, n * sizeof(int64_t),
+                                  hipMemcpyDeviceToHost, s->stream);
+    if (e != hipSuccess) return hip_fail(e, "server: series copy");
+    if ((j.req.flags & ISING_REQ_RETURN_SPINS) && j.req.spins_out) {
+      ising_status st = ising_get_spins(j.h, j.req.spins_out);
+      if (st != ISING_OK) return st;
+    }
+    s->leaving.emplace_back(t, off);
+    off += n;
+    s->arena.release(j.off, j.bytes);
+    s->table_used -= j.share;
+  }
+  hipError_t e = hipEventRecord(s->copied, s->stream);
+  return e == hipSuccess ? ISING_OK : hip_fail(e, "server: event");
+}
+
+// Retirement, second half (on the host, while the next quantum runs):
+// results, exact moment sums, completion time.
+ising_status end_retire(ising_server* s) {
+  if (s->leaving.empty()) return ISING_OK;
+  hipError_t e = hipEventSynchronize(s->copied);
+  if (e != hipSuccess) return hip_fail(e, "server: series copy");
+  for (const auto& lv : s->leaving) {
+    Job& j = s->jobs.at(lv.first);
+    const int64_t* series = s->staging + lv.second;
+    const size_t n = 2 * (size_t)j.req.n_sweeps;
+    if ((j.req.flags & ISING_REQ_RECORD_SERIES) && j.req.EM_series)
+      std::memcpy(j.req.EM_series, series, n * sizeof(int64_t));
+    j.res.E_final = series[n - 2];
+    j.res.M_final = series[n - 1];
+    j.res.sweeps_done = (uint64_t)j.done;
+    moments(series, j.req.n_sweeps, j.req.n_discard, &j.res);
+    j.res.status = ISING_OK;
+    j.res.t_done = now_s();
+    ising_destroy(j.h);
+    j.h = nullptr;
+    j.state = State::Done;
+    ++s->finished;
+  }
+  s->leaving.clear();
   return ISING_OK;
 }
 
-// One batched call over the active set; each lattice takes up to Q sweeps.
-ising_status run_quantum(ising_server* s, std::vector<ising_lattice*>& hs,
-                         std::vector<int64_t>& nsw, std::vector<int64_t*>& ems, int64_t n) {
-  BatchOptions opt = default_batch_options();
-  ising_status st = batch_sweeps(hs.data(), (int32_t)hs.size(), n, nsw.data(), ems.data(), opt,
-                                 s->table, s->table_bytes, nullptr);
-  if (st != ISING_OK) return st;
+// Wait for the quantum in flight and count its sweeps; `done` receives the
+// tickets that have finished (removed from the active set).
+ising_status finish_quantum(ising_server* s, std::vector<uint64_t>& done) {
+  if (!s->inflight) return ISING_OK;
   hipError_t e = hipStreamSynchronize(s->stream);
-  return e == hipSuccess ? ISING_OK : hip_fail(e, "server: quantum");
+  if (e != hipSuccess) return hip_fail(e, "server: quantum");
+  s->inflight = false;
+  for (size_t i = 0; i < s->ran.size(); ++i) {
+    Job& j = s->jobs.at(s->ran[i]);
+    j.h->sweep += (uint64_t)s->took[i];
+    j.done += s->took[i];
+  }
+  std::vector<uint64_t> still;
+  for (uint64_t t : s->active) {
+    Job& j = s->jobs.at(t);
+    if (j.done >= j.req.n_sweeps)
+      done.push_back(t);
+    else
+      still.push_back(t);
+  }
+  s->active.swap(still);
+  return ISING_OK;
 }
 
-ising_status step(ising_server* s) {
-  ising_status st = admit(s);
-  if (st != ISING_OK) return st;
-  if (s->active.empty()) return s->queue.empty() ? ISING_OK : ISING_AGAIN;
+// Enqueue one quantum of up to Q sweeps on every active lattice (direct
+// launches, no waiting); `wait` makes it synchronous and leaves nothing in
+// flight (the failed run of a fault-injected quantum).
+ising_status enqueue_quantum(ising_server* s, bool wait) {
   std::vector<ising_lattice*> hs;
   std::vector<int64_t> nsw;
   std::vector<int64_t*> ems;
+  s->ran.clear();
+  s->took.clear();
   int64_t n = 0;
   for (uint64_t t : s->active) {
     Job& j = s->jobs.at(t);
@@ -280,47 +348,73 @@ ising_status step(ising_server* s) {
     hs.push_back(j.h);
     nsw.push_back(take);
     ems.push_back(j.dev_series + 2 * j.done);
+    s->ran.push_back(t);
+    s->took.push_back(take);
     n = std::max(n, take);
   }
-  const int64_t q = s->quanta++;
-  if (s->faults.count(q)) {
-    // snapshot, run, declare the quantum failed, restore, run again
-    std::vector<std::vector<char>> snap(hs.size());
-    for (size_t i = 0; i < hs.size(); ++i) {
-      snap[i].resize(2 * (size_t)hs[i]->plane_words * sizeof(uint64_t));
-      hipError_t e = hipMemcpyAsync(snap[i].data(), hs[i]->planes, snap[i].size(),
-                                    hipMemcpyDeviceToHost, s->stream);
-      if (e != hipSuccess) return hip_fail(e, "server: snapshot");
-    }
-    st = run_quantum(s, hs, nsw, ems, n);
-    if (st != ISING_OK) return st;
-    for (size_t i = 0; i < hs.size(); ++i) {
-      hipError_t e = hipMemcpyAsync(hs[i]->planes, snap[i].data(), snap[i].size(),
-                                    hipMemcpyHostToDevice, s->stream);
-      if (e != hipSuccess) return hip_fail(e, "server: restore");
-    }
-    // the restore reads host memory that ends with this block
+  if (hs.empty()) return ISING_OK;
+  BatchOptions opt = default_batch_options();
+  opt.graph_chunk = 0;  // direct launches: nothing to keep alive but the image
+  opt.keep_image = &s->image;
+  ising_status st = batch_sweeps(hs.data(), (int32_t)hs.size(), n, nsw.data(), ems.data(), opt,
+                                 s->table, s->table_bytes, nullptr);
+  if (st != ISING_OK) {
+    (void)hipStreamSynchronize(s->stream);
+    return st;
+  }
+  if (wait) {
     hipError_t e = hipStreamSynchronize(s->stream);
-    if (e != hipSuccess) return hip_fail(e, "server: restore");
-    s->faults.erase(q);
-    ++s->recovered;
+    return e == hipSuccess ? ISING_OK : hip_fail(e, "server: quantum");
   }
-  st = run_quantum(s, hs, nsw, ems, n);
+  s->inflight = true;
+  return ISING_OK;
+}
+
+// One step: finish the quantum in flight, start retiring what it finished,
+// admit, enqueue the next quantum, and only then finish the retirement on
+// the host, so the GPU does not wait for the host's bookkeeping.
+ising_status step(ising_server* s) {
+  std::vector<uint64_t> done;
+  ising_status st = finish_quantum(s, done);
+  if (st == ISING_OK) st = begin_retire(s, done);
+  if (st == ISING_OK) st = admit(s);
   if (st != ISING_OK) return st;
-  std::vector<uint64_t> still;
-  for (size_t i = 0; i < s->active.size(); ++i) {
-    Job& j = s->jobs.at(s->active[i]);
-    j.h->sweep += (uint64_t)nsw[i];
-    j.done += nsw[i];
-    if (j.done >= j.req.n_sweeps) {
-      st = retire(s, j);
+  const int64_t q = s->quanta;
+  if (!s->active.empty()) {
+    ++s->quanta;
+    if (s->faults.count(q)) {
+      // snapshot, run, declare the quantum failed, restore; the quantum is
+      // then enqueued again below
+      st = end_retire(s);
       if (st != ISING_OK) return st;
-    } else {
-      still.push_back(j.ticket);
+      std::vector<std::vector<char>> snap(s->active.size());
+      for (size_t i = 0; i < s->active.size(); ++i) {
+        const ising_lattice* h = s->jobs.at(s->active[i]).h;
+        snap[i].resize(2 * (size_t)h->plane_words * sizeof(uint64_t));
+        hipError_t e = hipMemcpyAsync(snap[i].data(), h->planes, snap[i].size(),
+                                      hipMemcpyDeviceToHost, s->stream);
+        if (e != hipSuccess) return hip_fail(e, "server: snapshot");
+      }
+      st = enqueue_quantum(s, true);
+      if (st != ISING_OK) return st;
+      for (size_t i = 0; i < s->active.size(); ++i) {
+        const ising_lattice* h = s->jobs.at(s->active[i]).h;
+        hipError_t e = hipMemcpyAsync(h->planes, snap[i].data(), snap[i].size(),
+                                      hipMemcpyHostToDevice, s->stream);
+        if (e != hipSuccess) return hip_fail(e, "server: restore");
+      }
+      // the restore reads host memory that ends with this block
+      hipError_t e = hipStreamSynchronize(s->stream);
+      if (e != hipSuccess) return hip_fail(e, "server: restore");
+      s->faults.erase(q);
+      ++s->recovered;
     }
+    st = enqueue_quantum(s, false);
+    if (st != ISING_OK) return st;
   }
-  s->active.swap(still);
-  return (s->active.empty() && s->queue.empty()) ? ISING_OK : ISING_AGAIN;
+  st = end_retire(s);
+  if (st != ISING_OK) return st;
+  return (s->active.empty() && s->queue.empty() && !s->inflight) ? ISING_OK : ISING_AGAIN;
 }
 
 }  // namespace
@@ -453,6 +547,10 @@ ising_status ising_server_stats(const ising_server_t* s, int64_t out[6]) {
 ising_status ising_server_destroy(ising_server_t* s) {
   clear_error();
   if (!s) return ISING_OK;
+  // a quantum or a series copy may still be in flight
+  (void)hipStreamSynchronize(s->stream);
+  if (s->staging) (void)hipHostFree(s->staging);
+  if (s->copied) (void)hipEventDestroy(s->copied);
   for (auto& kv : s->jobs)
     if (kv.second.h) ising_destroy(kv.second.h);
   delete s;
