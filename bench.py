@@ -64,7 +64,7 @@ def parse():
     p.add_argument("--steps", type=int, default=5)
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--cpu-rows", type=int, default=4096,
+    p.add_argument("--cpu-rows", type=int, default=16384,
                    help="rows of the lattice in the CPU oracle's sample (a band with light-cone "
                         "margins, 2 sweeps) for the 262144^2 workloads")
     p.add_argument("--cpu-sweeps", type=int, default=16,
@@ -683,21 +683,37 @@ def cpu_baseline(w, sweeps, band_rows):
     import oracle
     threads = oracle.get_threads()
     kind = ["cold +1", "cold -1", "hot"][w.init]
+    one = None
     if w.L > 65536:
         n = 2
+
+        def band(rows):
+            t0 = time.perf_counter()
+            oracle.band_em(w.L, 1.0 / w.T, w.seed, w.stream_id, w.init, 0, 0, 0, rows)
+            t_start = time.perf_counter() - t0
+            t0 = time.perf_counter()
+            oracle.band_em(w.L, 1.0 / w.T, w.seed, w.stream_id, w.init, 0, n, 0, rows)
+            dt = time.perf_counter() - t0 - t_start
+            swept = (rows + 2 * (2 * n + 1) - 2) * w.L * n
+            return swept, dt, t_start
+
         rows = min(band_rows, w.L - 2 * (2 * n + 1))
-        t0 = time.perf_counter()
-        oracle.band_em(w.L, 1.0 / w.T, w.seed, w.stream_id, w.init, 0, 0, 0, rows)
-        t_start = time.perf_counter() - t0
-        t0 = time.perf_counter()
-        oracle.band_em(w.L, 1.0 / w.T, w.seed, w.stream_id, w.init, 0, n, 0, rows)
-        dt = time.perf_counter() - t0 - t_start
-        swept = (rows + 2 * (2 * n + 1) - 2) * w.L * n
+        swept, dt, t_start = band(rows)
         ups = swept / (dt * 1e9)
         sample = ("%d sweeps of rows 0..%d of the %dx%d lattice (%s start, T=%r) with their "
                   "%d-row light-cone margins: %.2e site updates in %.1f s (the start, %.1f s, "
                   "not counted)" % (n, rows - 1, w.L, w.L, kind, w.T, 2 * n + 1, swept, dt,
                                     t_start))
+        # one core on a band 1/32 as tall
+        oracle.set_threads(1)
+        try:
+            rows1 = max(rows // 32, 1)
+            swept1, dt1, _ = band(rows1)
+        finally:
+            oracle.set_threads(threads)
+        one = {"value": round(swept1 / (dt1 * 1e9), 4),
+               "sample": "the same on rows 0..%d, one thread: %.2e site updates in %.1f s"
+                         % (rows1 - 1, swept1, dt1)}
     else:
         s = oracle.init(w.L, w.seed, w.stream_id, w.init)
         t0 = time.perf_counter()
@@ -720,11 +736,15 @@ def cpu_baseline(w, sweeps, band_rows):
         paper_one = p.L * p.L * 2 / ((time.perf_counter() - t1) * 1e9)
     finally:
         oracle.set_threads(threads)
-    return {"value": ups, "unit": "spin updates/ns", "cores": threads, "kind": "oracle",
-            "sample": sample, "cpu_model": cpu_model(),
+    out = {"value": ups, "unit": "spin updates/ns", "cores": threads, "kind": "oracle",
+           "sample": sample, "cpu_model": cpu_model()}
+    if one is not None:
+        out["one_core"] = one
+    out.update({
             "paper_point": {"workload": "%dx%d, T = 0.99 T_C, 10 sweeps (all cores), 2 sweeps "
                                         "(one core)" % (p.L, p.L),
-                            "value": round(paper_all, 4), "value_1core": round(paper_one, 4)}}
+                            "value": round(paper_all, 4), "value_1core": round(paper_one, 4)}})
+    return out
 
 
 def time_plain(torch, ising, dev, stream, w, steps, warmup, check=True):
