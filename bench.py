@@ -100,7 +100,10 @@ def parse():
     p.add_argument("--no-pool", action="store_true",
                    help="skip the plain workload with Boltzmann-pattern pools")
     p.add_argument("--no-autotune", action="store_true",
-                   help="skip the autotuner report (profiling runs: no trial launches)")
+                   help="skip the autotuners (profiling runs: no trial launches)")
+    p.add_argument("--batched-shape", default=None,
+                   help="rpw_max,wg_per_cu,graph_chunk of the batched grid's fused launches "
+                        "instead of the batched autotuner's pick (profiling runs)")
     p.add_argument("--served-requests", type=int, default=2000,
                    help="requests of the 2000-request Poisson stream to serve (default: all, "
                         "about 160 s)")
@@ -316,14 +319,21 @@ def crossings_where_resolved(ising, sizes, checks, fine, curves):
     return out
 
 
-def bench_batched(torch, ising, dev, sweeps):
+def bench_batched(torch, ising, dev, sweeps, autotune=True):
     """224 lattices (L in 64..4096 x 32 temperatures) advanced together:
     two fused launches per sweep over all lattices, replayed from captured
-    hipGraph chunks."""
+    hipGraph chunks, in the fused shape the batched autotuner picks on
+    copies of the same lattices."""
     grid = workloads.fss_grid()
     lats = [ising.Lattice(g.L, seed=g.seed, stream_id=g.stream_id, init=g.init, beta=1.0 / g.T,
                           device=dev) for g in grid]
     EMs = [torch.empty((sweeps, 2), dtype=torch.int64, device=dev) for _ in grid]
+    pick = None
+    if autotune:
+        t_tune = time.perf_counter()
+        pick = ising.multi_autotune(lats, 128)
+        pick = {k: (round(v, 1) if isinstance(v, float) else v) for k, v in pick.items()}
+        pick["seconds"] = round(time.perf_counter() - t_tune, 2)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ising.multi_sweep(lats, sweeps, EMs)  # synchronises
@@ -356,6 +366,9 @@ def bench_batched(torch, ising, dev, sweeps):
                     "%d sweeps each, per-sweep int64 E/M; two fused launches per sweep over "
                     "all lattices, replayed from hipGraph chunks" % sweeps,
         "seconds": round(dt, 3),
+        "shape": {k: v for k, v in ising.batch_tuning_get().items()
+                  if k in ("rpw_max", "wg_per_cu", "graph_chunk", "installed")},
+        "autotuner_pick": pick,
         "plain_one_by_one": {"value": round(plain_updates / (dt_plain * 1e9), 2),
                              "sweeps": plain_sweeps},
         "binder_U4": {str(L): {"%.4f" % workloads.FSS_TEMPS[i]: round(v[i], 4) for i in tidx}
@@ -904,7 +917,12 @@ def main():
     if not args.no_batched:
         print("bench: batched FSS grid (%d sweeps)" % args.batched_sweeps, file=sys.stderr,
               flush=True)
-        result["batched"] = bench_batched(torch, ising, dev, args.batched_sweeps)
+        if args.batched_shape:
+            ising.batch_tuning_set(*[int(v) for v in args.batched_shape.split(",")])
+        result["batched"] = bench_batched(torch, ising, dev, args.batched_sweeps,
+                                          autotune=not (args.no_autotune or args.batched_shape))
+        # the pick is the grid's: later legs (the server) keep the built-in shape
+        ising.batch_tuning_clear()
         if not args.no_fss_proof:
             print("bench: FSS proof of concept (small lattices, long runs)", file=sys.stderr,
                   flush=True)

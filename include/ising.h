@@ -262,6 +262,64 @@ ISING_API ising_status ising_tuning_lookup(int64_t L, ising_tuning *out);
 ISING_API ising_status ising_tuning_clear(void);
 
 /* ---------------------------------------------------------------- */
+/* Batched autotuner: the fused kernel's tile shape, grid and graph   */
+/* chunk for ising_multi_sweep.                                       */
+/* ---------------------------------------------------------------- */
+
+typedef struct {
+    int32_t form;           /* the faster form on the timed batch: 0 fused, 1 packed
+                               (informational: the cost model still chooses per call) */
+    int32_t rpw_max;        /* fused tiles: a lattice takes the largest of 1, 2, 4 row
+                               groups per wave up to this that leaves it >= 128 r tiles
+                               of one row group (built-in: 2); 1, 2 or 4 */
+    int32_t wg_per_cu;      /* fused grid: workgroups per compute unit, 1..8 (built-in 8) */
+    int32_t graph_chunk;    /* sweeps per captured hipGraph chunk, 0..4096 (0: no graph;
+                               built-in 32) */
+    double updates_per_ns;          /* rate of this fused shape on the timed batch */
+    double default_updates_per_ns;  /* the built-in fused shape on the same batch */
+    double packed_updates_per_ns;   /* the packed form on the same batch (0: not timed,
+                                       the cost model puts it far behind) */
+} ising_batch_tuning;
+
+/* Device bytes ising_multi_autotune needs for these handles and
+ * trial_sweeps (>= 1): copies of every lattice, their per-sweep (E, M) for
+ * 2 trial_sweeps sweeps, and the largest work buffer of any candidate.
+ * Host only. */
+ISING_API ising_status ising_multi_autotune_bytes(ising_t *const *hs, int32_t count,
+                                                  int32_t trial_sweeps, size_t *bytes);
+
+/*
+ * Time the batched sweep's fused shapes on copies of these lattices (same
+ * sides, seeds, stream ids, starts and betas, made in dev_buf: device,
+ * 256-byte aligned, at least ising_multi_autotune_bytes; the handles
+ * themselves are not touched): rpw_max in {1, 2, 4} x workgroups per CU in
+ * {8, 6, 4} with graph chunk 32, then chunks {8, 16, 64} at the best of
+ * those, and the packed form when the cost model does not put it far
+ * behind.  A candidate's rate is trial_sweeps sweeps of updates over the
+ * time of a 2 trial_sweeps call less that of a trial_sweeps call (the
+ * table upload and graph capture cancel), with per-sweep (E, M) recorded.
+ * Installs the fastest fused shape for every later batched call
+ * (ising_multi_sweep, _form, _static and the server) and returns it in
+ * *out.  Results are bit-identical for every shape.  Runs on the handles'
+ * stream and synchronises it.  Errors: EINVAL, ENOMEM (buffer too small or
+ * misaligned), EDEVICE.
+ */
+ISING_API ising_status ising_multi_autotune(ising_t *const *hs, int32_t count,
+                                            int32_t trial_sweeps, void *dev_buf,
+                                            size_t dev_bytes, ising_batch_tuning *out);
+
+/* Install a fused shape (rpw_max, wg_per_cu, graph_chunk of *t; the other
+ * fields are ignored), for example one an earlier run measured. */
+ISING_API ising_status ising_batch_tuning_set(const ising_batch_tuning *t);
+
+/* The fused shape batched calls use now; *installed is 1 if it was
+ * installed (rates as measured), 0 for the built-in one (rates 0). */
+ISING_API ising_status ising_batch_tuning_get(ising_batch_tuning *out, int32_t *installed);
+
+/* Back to the built-in fused shape. */
+ISING_API ising_status ising_batch_tuning_clear(void);
+
+/* ---------------------------------------------------------------- */
 /* The paper's own random numbers (alternative dynamics).            */
 /* ---------------------------------------------------------------- */
 

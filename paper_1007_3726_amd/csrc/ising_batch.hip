@@ -326,15 +326,17 @@ static void classify(ising_lattice* const* hs, int32_t count, const BatchOptions
     // 2^32 words or more (L >= 741456) take the plain path
     if (tile_args(hs[i], &ta) && hs[i]->plane_words < (1ll << 32)) {
       // fine tiles balance best across the flat list; lattices with many
-      // tiles take two row groups per wave (the packed kernel's LDS
-      // staging bounds the shape)
-      ta.RPW = 1;
-      int64_t TR = 4 * (int64_t)ta.R;
-      if (((hs[i]->L + TR - 1) / TR) * ta.segs >= 256 &&
-          (2 * TR + 2) * (ta.TW + 2) <= kTileLdsMaxWords) {
-        ta.RPW = 2;
-        TR *= 2;
+      // tiles take up to rpw_max row groups per wave (the packed kernel's
+      // LDS staging bounds the shape)
+      const int64_t TR1 = 4 * (int64_t)ta.R;
+      const int64_t tiles1 = ((hs[i]->L + TR1 - 1) / TR1) * ta.segs;
+      int rpw = 1;
+      for (int r = 2; r <= opt.rpw_max; r *= 2) {
+        if (tiles1 < 128 * (int64_t)r || (r * TR1 + 2) * (ta.TW + 2) > kTileLdsMaxWords) break;
+        rpw = r;
       }
+      ta.RPW = rpw;
+      const int64_t TR = TR1 * rpw;
       ta.tiles = ((hs[i]->L + TR - 1) / TR) * ta.segs;
       targs[i] = ta;
       tiled.push_back(i);
@@ -448,7 +450,8 @@ extern "C" ising_status ising_batch_plan(const int64_t* Ls, int32_t count, int32
   return ISING_OK;
 }
 
-static ising_status check_batch(ising_t* const* hs, int32_t count, int64_t n, const char* who) {
+namespace ising {
+ising_status check_batch(ising_t* const* hs, int32_t count, int64_t n, const char* who) {
   if (!hs || count < 0 || n < 0) return fail(ISING_EINVAL, "%s: bad arguments", who);
   for (int32_t i = 0; i < count; ++i) {
     if (!hs[i]) return fail(ISING_EINVAL, "%s: NULL handle %d", who, i);
@@ -466,6 +469,7 @@ static ising_status check_batch(ising_t* const* hs, int32_t count, int64_t n, co
   }
   return ISING_OK;
 }
+}  // namespace ising
 
 // ---------------------------------------------------------------------
 // The allocation-free variant (ising_multi_sweep_static): the task tables
@@ -532,10 +536,13 @@ extern "C" ising_status ising_multi_sweep_work_bytes(ising_t* const* hs, int32_t
   *bytes = 0;
   ising_status st = check_batch(hs, count, 0, "ising_multi_sweep_work_bytes");
   if (st != ISING_OK) return st;
-  // every form the caller may force: count each tiled lattice (a lone large
-  // lattice takes the plain path only when the cost model chooses)
+  // every form the caller may force and every fused shape the batched
+  // autotuner may install: count each tiled lattice (a lone large lattice
+  // takes the plain path only when the cost model chooses) with its finest
+  // tiles
   BatchOptions opt = default_batch_options();
   opt.force_form = 0;
+  opt.rpw_max = 1;
   *bytes = batch_work_bytes(hs, count, opt);
   return ISING_OK;
 }

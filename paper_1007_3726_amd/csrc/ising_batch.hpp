@@ -32,6 +32,10 @@ struct BatchOptions {
   PlanModel model;
   int force_form;   // -1: cost model, 0: fused, 1: packed
   int graph_chunk;  // sweeps per captured hipGraph chunk (0: no graph)
+  // row groups per wave of a lattice's tiles: the largest r in {1, 2, 4},
+  // r <= rpw_max, for which the lattice has at least 128 r tiles of one row
+  // group per wave and the packed kernel's LDS staging still fits
+  int rpw_max = 2;
   // when set (with graph_chunk 0): the table image is kept here, since it
   // must outlive its asynchronous upload, and the call returns without
   // waiting for the stream; the caller synchronises before it reuses the
@@ -40,7 +44,11 @@ struct BatchOptions {
 };
 
 PlanModel default_model();
+// The built-in batched options, with the batched autotuner's installed
+// fused shape (rpw_max, workgroups per CU, graph chunk) if there is one.
 BatchOptions default_batch_options();
+// Argument checks shared by the batched entry points (n: sweeps to come).
+ising_status check_batch(ising_t* const* hs, int32_t count, int64_t n, const char* who);
 BatchPlan plan_batch(const std::vector<int64_t>& tiles, int cus, const PlanModel& model);
 // Device bytes of the work buffer batch_sweeps needs for these handles
 // (0 when every lattice takes the plain path).

@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <mutex>
 #include <vector>
 
@@ -20,6 +21,9 @@ namespace {
 
 std::mutex g_tune_mutex;
 std::vector<ising_tuning> g_table;
+// the batched autotuner's installed fused shape
+bool g_batch_set = false;
+ising_batch_tuning g_batch;
 
 int64_t class_lo(int64_t L) {
   int64_t c = 1;
@@ -62,6 +66,13 @@ BatchOptions default_batch_options() {
   o.model = default_model();
   o.force_form = -1;
   o.graph_chunk = 32;
+  o.rpw_max = 2;
+  std::lock_guard<std::mutex> lock(g_tune_mutex);
+  if (g_batch_set) {
+    o.rpw_max = g_batch.rpw_max;
+    o.model.wg_per_cu = g_batch.wg_per_cu;
+    o.graph_chunk = g_batch.graph_chunk;
+  }
   return o;
 }
 
@@ -208,6 +219,233 @@ ising_status ising_tuning_clear(void) {
   clear_error();
   std::lock_guard<std::mutex> lock(g_tune_mutex);
   g_table.clear();
+  return ISING_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------
+// Batched autotuner
+// ---------------------------------------------------------------------
+namespace ising {
+namespace {
+
+size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+bool valid_batch_shape(const ising_batch_tuning& t) {
+  return (t.rpw_max == 1 || t.rpw_max == 2 || t.rpw_max == 4) && t.wg_per_cu >= 1 &&
+         t.wg_per_cu <= 8 && t.graph_chunk >= 0 && t.graph_chunk <= 4096;
+}
+
+// Layout of the autotuner's buffer: lattice copies, then their (E, M)
+// series of 2 m sweeps, then the work buffer.
+struct TuneLayout {
+  std::vector<size_t> lat, em;
+  size_t work = 0, work_bytes = 0, bytes = 0;
+};
+
+TuneLayout tune_layout(ising_t* const* hs, int32_t count, int64_t m) {
+  TuneLayout t;
+  size_t off = 0;
+  for (int32_t i = 0; i < count; ++i) {
+    t.lat.push_back(off);
+    off += align256(lattice_bytes(hs[i]->L));
+  }
+  for (int32_t i = 0; i < count; ++i) {
+    t.em.push_back(off);
+    off += align256((size_t)(2 * m) * 2 * sizeof(int64_t));
+  }
+  BatchOptions opt = default_batch_options();
+  opt.force_form = 0;
+  opt.rpw_max = 1;  // the finest tiles need the most table space
+  t.work = off;
+  t.work_bytes = batch_work_bytes(hs, count, opt);
+  t.bytes = off + align256(t.work_bytes);
+  return t;
+}
+
+}  // namespace
+}  // namespace ising
+
+extern "C" {
+
+ising_status ising_multi_autotune_bytes(ising_t* const* hs, int32_t count, int32_t trial_sweeps,
+                                        size_t* bytes) {
+  clear_error();
+  if (!bytes || trial_sweeps < 1) return fail(ISING_EINVAL, "ising_multi_autotune_bytes: bad args");
+  *bytes = 0;
+  ising_status st = check_batch(hs, count, 0, "ising_multi_autotune_bytes");
+  if (st != ISING_OK) return st;
+  *bytes = tune_layout(hs, count, trial_sweeps).bytes;
+  return ISING_OK;
+}
+
+ising_status ising_multi_autotune(ising_t* const* hs, int32_t count, int32_t trial_sweeps,
+                                  void* dev_buf, size_t dev_bytes, ising_batch_tuning* out) {
+  clear_error();
+  if (!out || trial_sweeps < 1 || count < 1)
+    return fail(ISING_EINVAL, "ising_multi_autotune: bad arguments");
+  ising_status st = check_batch(hs, count, 0, "ising_multi_autotune");
+  if (st != ISING_OK) return st;
+  const int64_t m = trial_sweeps;
+  const TuneLayout lay = tune_layout(hs, count, m);
+  if (!dev_buf || ((uintptr_t)dev_buf & 255) || dev_bytes < lay.bytes)
+    return fail(ISING_ENOMEM,
+                "ising_multi_autotune: needs a 256-byte aligned buffer of %zu bytes (got %zu)",
+                lay.bytes, dev_buf ? dev_bytes : (size_t)0);
+  char* base = (char*)dev_buf;
+  const hipStream_t stream = hs[0]->stream;
+  // copies of the lattices, each at the start of its own sweep counter
+  std::vector<ising_t*> tmp(count, nullptr);
+  std::vector<int64_t*> ems(count);
+  for (int32_t i = 0; i < count && st == ISING_OK; ++i) {
+    const ising_lattice* h = hs[i];
+    st = ising_create(h->L, h->seed, h->stream_id, h->init, base + lay.lat[i],
+                      align256(lattice_bytes(h->L)), stream, &tmp[i]);
+    if (st == ISING_OK) st = ising_set_beta(tmp[i], h->beta);
+    ems[i] = (int64_t*)(base + lay.em[i]);
+  }
+  void* work = base + lay.work;
+  int64_t updates = 0;  // spin updates of one sweep of the batch
+  for (int32_t i = 0; i < count; ++i) updates += hs[i]->L * hs[i]->L;
+
+  // seconds of a synchronous batched call of n sweeps
+  auto run = [&](const BatchOptions& opt, int64_t n, double* sec) -> ising_status {
+    const auto t0 = std::chrono::steady_clock::now();
+    ising_status s2 = batch_sweeps(tmp.data(), count, n, nullptr, ems.data(), opt, work,
+                                   lay.work_bytes, nullptr);
+    if (s2 != ISING_OK) return s2;
+    hipError_t e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hip_fail(e, "ising_multi_autotune: synchronize");
+    *sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    for (ising_t* h : tmp) h->sweep += (uint64_t)n;
+    return ISING_OK;
+  };
+  // updates/ns of one candidate: m sweeps over t(2 m) - t(m)
+  auto rate = [&](const BatchOptions& opt, double* r) -> ising_status {
+    double t1 = 0.0, t2 = 0.0;
+    ising_status s2 = run(opt, m, &t1);
+    if (s2 == ISING_OK) s2 = run(opt, 2 * m, &t2);
+    if (s2 != ISING_OK) return s2;
+    const double dt = t2 > t1 ? t2 - t1 : t2 / 2.0;
+    *r = (double)updates * (double)m / (dt * 1e9);
+    return ISING_OK;
+  };
+  auto shape = [](int rpw_max, int wg, int chunk) {
+    BatchOptions o = default_batch_options();
+    o.force_form = 0;
+    o.rpw_max = rpw_max;
+    o.model = default_model();
+    o.model.wg_per_cu = wg;
+    o.graph_chunk = chunk;
+    return o;
+  };
+
+  ising_batch_tuning best;
+  best.form = 0;
+  best.rpw_max = 2;
+  best.wg_per_cu = 8;
+  best.graph_chunk = 32;
+  best.updates_per_ns = -1.0;
+  best.default_updates_per_ns = 0.0;
+  best.packed_updates_per_ns = 0.0;
+  if (st == ISING_OK) {  // warm-up: first launches of the kernels
+    double t = 0.0;
+    st = run(shape(2, 8, 32), m, &t);
+  }
+  for (int rpw : {1, 2, 4})
+    for (int wg : {8, 6, 4}) {
+      if (st != ISING_OK) break;
+      double r = 0.0;
+      st = rate(shape(rpw, wg, 32), &r);
+      if (st != ISING_OK) break;
+      if (rpw == 2 && wg == 8) best.default_updates_per_ns = r;
+      if (r > best.updates_per_ns) {
+        best.rpw_max = rpw;
+        best.wg_per_cu = wg;
+        best.updates_per_ns = r;
+      }
+    }
+  for (int chunk : {8, 16, 64}) {
+    if (st != ISING_OK) break;
+    double r = 0.0;
+    st = rate(shape(best.rpw_max, best.wg_per_cu, chunk), &r);
+    if (st != ISING_OK) break;
+    if (r > best.updates_per_ns) {
+      best.graph_chunk = chunk;
+      best.updates_per_ns = r;
+    }
+  }
+  if (st == ISING_OK) {
+    // the packed form, unless the cost model puts it far behind (one
+    // workgroup per lattice: a large lattice alone would take seconds)
+    std::vector<int64_t> tiles;
+    BatchOptions o = shape(best.rpw_max, best.wg_per_cu, best.graph_chunk);
+    for (int32_t i = 0; i < count; ++i) {
+      TileArgs ta;
+      if (tile_args(hs[i], &ta)) tiles.push_back(tile_cost(ta.tiles, ta.RPW));
+    }
+    int dev_cus = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, hs[0]->device) == hipSuccess)
+      dev_cus = prop.multiProcessorCount;
+    if (!tiles.empty() && dev_cus > 0) {
+      const BatchPlan plan = plan_batch(tiles, dev_cus, o.model);
+      if (plan.packed_s <= 4.0 * plan.fused_s) {
+        o.force_form = 1;
+        double r = 0.0;
+        st = rate(o, &r);
+        if (st == ISING_OK) {
+          best.packed_updates_per_ns = r;
+          if (r > best.updates_per_ns) best.form = 1;
+        }
+      }
+    }
+  }
+  for (ising_t* h : tmp)
+    if (h) ising_destroy(h);
+  if (st != ISING_OK) return st;
+  {
+    std::lock_guard<std::mutex> lock(g_tune_mutex);
+    g_batch = best;
+    g_batch_set = true;
+  }
+  *out = best;
+  return ISING_OK;
+}
+
+ising_status ising_batch_tuning_set(const ising_batch_tuning* t) {
+  clear_error();
+  if (!t || !valid_batch_shape(*t)) return fail(ISING_EINVAL, "ising_batch_tuning_set: bad shape");
+  std::lock_guard<std::mutex> lock(g_tune_mutex);
+  g_batch = *t;
+  g_batch_set = true;
+  return ISING_OK;
+}
+
+ising_status ising_batch_tuning_get(ising_batch_tuning* out, int32_t* installed) {
+  clear_error();
+  if (!out || !installed) return fail(ISING_EINVAL, "ising_batch_tuning_get: bad args");
+  std::lock_guard<std::mutex> lock(g_tune_mutex);
+  *installed = g_batch_set ? 1 : 0;
+  if (g_batch_set) {
+    *out = g_batch;
+  } else {
+    out->form = 0;
+    out->rpw_max = 2;
+    out->wg_per_cu = 8;
+    out->graph_chunk = 32;
+    out->updates_per_ns = 0.0;
+    out->default_updates_per_ns = 0.0;
+    out->packed_updates_per_ns = 0.0;
+  }
+  return ISING_OK;
+}
+
+ising_status ising_batch_tuning_clear(void) {
+  clear_error();
+  std::lock_guard<std::mutex> lock(g_tune_mutex);
+  g_batch_set = false;
   return ISING_OK;
 }
 

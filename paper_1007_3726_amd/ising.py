@@ -56,6 +56,13 @@ class ising_tuning(ctypes.Structure):
                 ("updates_per_ns", ctypes.c_double)]
 
 
+class ising_batch_tuning(ctypes.Structure):
+    _fields_ = [("form", ctypes.c_int32), ("rpw_max", ctypes.c_int32),
+                ("wg_per_cu", ctypes.c_int32), ("graph_chunk", ctypes.c_int32),
+                ("updates_per_ns", ctypes.c_double), ("default_updates_per_ns", ctypes.c_double),
+                ("packed_updates_per_ns", ctypes.c_double)]
+
+
 class ising_result(ctypes.Structure):
     _fields_ = [("ticket", ctypes.c_uint64), ("status", ctypes.c_int32),
                 ("E_final", ctypes.c_int64), ("M_final", ctypes.c_int64),
@@ -107,6 +114,12 @@ def lib():
         "ising_tuning_get": ([P(ising_tuning), i32, P(i32)], i32),
         "ising_tuning_clear": ([], i32),
         "ising_tuning_lookup": ([i64, P(ising_tuning)], i32),
+        "ising_multi_autotune_bytes": ([P(vp), i32, i32, P(ctypes.c_size_t)], i32),
+        "ising_multi_autotune": ([P(vp), i32, i32, vp, ctypes.c_size_t, P(ising_batch_tuning)],
+                                 i32),
+        "ising_batch_tuning_set": ([P(ising_batch_tuning)], i32),
+        "ising_batch_tuning_get": ([P(ising_batch_tuning), P(i32)], i32),
+        "ising_batch_tuning_clear": ([], i32),
         "ising_server_create": ([vp, ctypes.c_size_t, vp, i32, P(vp)], i32),
         "ising_batch_submit": ([vp, P(ising_request), i32, P(u64)], i32),
         "ising_server_step": ([vp], i32),
@@ -485,6 +498,45 @@ def multi_sweep(lattices: Sequence[Lattice], n: int, EMs=None, form=None, graph_
     check(lib().ising_multi_sweep_form(arr, len(lattices), int(n), em_arr, f, int(graph_chunk),
                                        work.data_ptr() if work is not None else None,
                                        int(nbytes.value)))
+
+
+_BATCH_TUNING_KEYS = ["form", "rpw_max", "wg_per_cu", "graph_chunk", "updates_per_ns",
+                      "default_updates_per_ns", "packed_updates_per_ns"]
+
+
+def multi_autotune(lattices: Sequence[Lattice], trial_sweeps: int = 128) -> dict:
+    """Time the batched sweep's fused shapes on copies of these lattices
+    (the lattices themselves are not advanced) and install the fastest for
+    later batched calls; returns it."""
+    arr = (ctypes.c_void_p * max(len(lattices), 1))(*[lat.h.value for lat in lattices])
+    nbytes = ctypes.c_size_t()
+    check(lib().ising_multi_autotune_bytes(arr, len(lattices), int(trial_sweeps),
+                                           ctypes.byref(nbytes)))
+    # the call synchronises the lattices' stream before it returns
+    buf = _dev_alloc(nbytes.value, lattices[0].device)
+    out = ising_batch_tuning()
+    check(lib().ising_multi_autotune(arr, len(lattices), int(trial_sweeps), buf.data_ptr(),
+                                     int(nbytes.value), ctypes.byref(out)))
+    return {k: getattr(out, k) for k in _BATCH_TUNING_KEYS}
+
+
+def batch_tuning_get() -> dict:
+    """The fused shape batched calls use now, and whether it was installed."""
+    out = ising_batch_tuning()
+    inst = ctypes.c_int32()
+    check(lib().ising_batch_tuning_get(ctypes.byref(out), ctypes.byref(inst)))
+    d = {k: getattr(out, k) for k in _BATCH_TUNING_KEYS}
+    d["installed"] = bool(inst.value)
+    return d
+
+
+def batch_tuning_set(rpw_max: int, wg_per_cu: int, graph_chunk: int):
+    t = ising_batch_tuning(0, int(rpw_max), int(wg_per_cu), int(graph_chunk), 0.0, 0.0, 0.0)
+    check(lib().ising_batch_tuning_set(ctypes.byref(t)))
+
+
+def batch_tuning_clear():
+    check(lib().ising_batch_tuning_clear())
 
 
 def reweight(EMs, betas0, discards, task_lattice, task_beta, nblocks: int, stream=None):

@@ -210,3 +210,49 @@ def test_whole_fss_grid_against_the_oracle(I):
             got = lat.get_window(x0, y0, 40, 12)
             want = oracle.window(g.L, beta, g.seed, g.stream_id, g.init, 0, n, x0, y0, 40, 12)
             assert np.array_equal(got, want), (g, x0, y0)
+
+
+@pytest.mark.parametrize("shape", [(1, 8, 32), (4, 8, 32), (2, 4, 8), (4, 6, 64), (1, 6, 0)])
+def test_every_fused_shape_matches_plain(I, shape):
+    """The batched autotuner's candidate shapes (row groups per wave up to
+    rpw_max, workgroups per CU, graph chunk) installed one at a time: the
+    fused form stays bit-identical to the plain path.  4096^2 and 8192^2
+    take four row groups per wave under rpw_max 4."""
+    rpw_max, wg, chunk = shape
+    H = workloads.INIT_HOT
+    specs = MIXED + [(4096, 2.27, 10, 10, H), (8192, 2.4, 11, 11, H), (520, 2.3, 12, 12, H)]
+    _say("case fused shape rpw_max=%d wg=%d chunk=%d" % shape)
+    I.batch_tuning_set(rpw_max, wg, chunk)
+    try:
+        assert I.batch_tuning_get()["installed"]
+        _batched_vs_plain(I, specs, 2 * chunk + 3 if chunk else 6, chunks=1, form="fused")
+    finally:
+        I.batch_tuning_clear()
+
+
+def test_multi_autotune_installs_a_shape_and_leaves_the_lattices(I):
+    import torch
+    H = workloads.INIT_HOT
+    specs = [(512, 2.27, 1, 1, H), (1024, 2.3, 2, 2, H), (2048, 2.25, 3, 3, H),
+             (4096, 2.269, 4, 4, H), (130, 2.4, 5, 5, H), (6, 2.0, 6, 6, H)]
+    lats = _make(I, specs)
+    EM = [torch.empty((3, 2), dtype=torch.int64, device="cuda") for _ in specs]
+    I.multi_sweep(lats, 3, EM)
+    before = [(lat.get_spins(), lat.sweep_count) for lat in lats]
+    _say("case multi_autotune")
+    try:
+        pick = I.multi_autotune(lats, 16)
+        _say("pick", pick)
+        for (s, c), lat in zip(before, lats):
+            assert lat.sweep_count == c
+            assert np.array_equal(lat.get_spins(), s)
+        inst = I.batch_tuning_get()
+        assert inst["installed"]
+        for k in ("rpw_max", "wg_per_cu", "graph_chunk", "updates_per_ns"):
+            assert inst[k] == pick[k]
+        assert pick["rpw_max"] in (1, 2, 4) and 1 <= pick["wg_per_cu"] <= 8
+        assert pick["updates_per_ns"] >= pick["default_updates_per_ns"] > 0
+        # the installed shape gives the plain path's results
+        _batched_vs_plain(I, specs, 40, chunks=2)
+    finally:
+        I.batch_tuning_clear()
