@@ -115,15 +115,18 @@ ISING_API ising_status ising_get_thresholds(const ising_t *h, uint32_t t[2]);
  * Enqueue n >= 0 full sweeps (colour 0 then colour 1, section 3) with sweep
  * counters h.sweep ... h.sweep + n - 1, then advance h.sweep by n.
  * If dev_EM is not NULL it is a device array of n x 2 int64: after sweep k
- * it holds E_k = -sum_<ij> S_i S_j and M_k = sum_i S_i (exact).
+ * it holds E_k = -sum_<ij> S_i S_j (Eq. (1) with J = 1, no field) and
+ * M_k = sum_i S_i (the magnetisation section 5.2 reduces), both exact.
  * Errors: EINVAL (no beta set, n < 0), ERANGE (counter overflow), EDEVICE.
  */
 ISING_API ising_status ising_sweep(ising_t *h, int64_t n, int64_t *dev_EM);
 
-/* E and M of the current state into host *E, *M.  Synchronises the stream. */
+/* E (Eq. (1), J = 1, no field) and M (sum of the spins, section 5.2) of
+ * the current state into host *E, *M, exact.  Synchronises the stream. */
 ISING_API ising_status ising_measure(ising_t *h, int64_t *E, int64_t *M);
 
-/* Copy all spins to host (L*L int8, +1/-1, row-major [y][x]).  Synchronises. */
+/* Copy all spins to host (L*L int8, +1/-1, row-major [y][x]; on the device
+ * a set bit is a +1 spin, section 5.2's one bit per spin).  Synchronises. */
 ISING_API ising_status ising_get_spins(ising_t *h, int8_t *host);
 
 /* Overwrite all spins from host (L*L int8, each +1 or -1, else EINVAL).
