@@ -172,7 +172,9 @@ def bench_served(torch, ising, dev, n_req, arena_gib, quantum, plain_n, plain_ra
            "p99_latency_s": round(float(np.percentile(lat, 99)), 3),
            "mean_latency_s": round(float(lat.mean()), 3),
            "wall_s": round(wall, 3), "arena_gib": arena_gib, "quantum_sweeps": quantum,
-           "peak_arena_bytes": stats["peak_bytes"], "quanta": stats["quanta"]}
+           "peak_arena_bytes": stats["peak_bytes"], "quanta": stats["quanta"],
+           "valu_roof_frac": round(work_done / (wall * 1e9) * ALU_OPS_PER_UPDATE * 1e9
+                                   / VALU_PEAK_LANE_OPS, 4)}
     # capacity: the first requests of the stream all queued at once, so the
     # server never waits for an arrival
     if cap_n > 0:
@@ -192,7 +194,9 @@ def bench_served(torch, ising, dev, n_req, arena_gib, quantum, plain_n, plain_ra
         srv.close()
         cwork = sum(r.L * r.L * r.sweeps for r in sub)
         out["capacity"] = {"requests": cap_n, "value": round(cwork / (dtc * 1e9), 2),
-                           "seconds": round(dtc, 3)}
+                           "seconds": round(dtc, 3),
+                           "valu_roof_frac": round(cwork / dtc * ALU_OPS_PER_UPDATE
+                                                   / VALU_PEAK_LANE_OPS, 4)}
     # the same requests one at a time through the plain path (FIFO, no overlap)
     if plain_n > 0:
         sub = stream[:plain_n]
@@ -362,6 +366,7 @@ def bench_batched(torch, ising, dev, sweeps, autotune=True):
     fss = bench_fss(torch, ising, dev, grid, EMs, discard)
     return {
         "value": round(updates / (dt * 1e9), 2), "unit": "spin updates/ns",
+        "valu_roof_frac": round(updates / dt * ALU_OPS_PER_UPDATE / VALU_PEAK_LANE_OPS, 4),
         "workload": "224 lattices, L in {64..4096} x 32 T in [2.20, 2.34], hot start, "
                     "%d sweeps each, per-sweep int64 E/M; two fused launches per sweep over "
                     "all lattices, replayed from hipGraph chunks" % sweeps,
