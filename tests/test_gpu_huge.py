@@ -102,7 +102,7 @@ def test_huge_lattice_windows(I, w):
 def _windows_and_invariants(I, L, T, seed, n, spots):
     lat = I.Lattice(L, seed=seed, stream_id=0, init=workloads.INIT_HOT, beta=1.0 / T)
     EM = lat.sweep_em(n).cpu().numpy()
-    _check_golden((L, T, seed, 0, workloads.INIT_HOT), EM, required=False)
+    _check_golden((L, T, seed, 0, workloads.INIT_HOT), EM, required=True)
     N = L * L
     assert np.all(EM[:, 0] % 4 == 0) and np.all((EM[:, 1] - N) % 2 == 0)
     assert np.all(np.abs(EM[:, 0]) <= 2 * N) and np.all(np.abs(EM[:, 1]) <= N)
