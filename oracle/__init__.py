@@ -61,6 +61,12 @@ def lib():
         L.oracle_pool_sweeps.restype = i32
         L.oracle_band_em.argtypes = [i64, u32, u32, u64, u32, i32, u32, i64, i64, i64, p64]
         L.oracle_band_em.restype = i32
+        L.oracle_pool_window.argtypes = [i64, u64, u32, i32, u32, i64, i32, i32, pu64, pu64,
+                                         i64, i64, i64, i64, p8]
+        L.oracle_pool_window.restype = i32
+        L.oracle_lcg_window.argtypes = [i64, u32, u32, u64, u32, i32, i64, i64, i64, i64, i64,
+                                        p8]
+        L.oracle_lcg_window.restype = i32
         L.oracle_get_threads.argtypes = []
         L.oracle_get_threads.restype = i32
         L.oracle_set_threads.argtypes = [i32]
@@ -230,6 +236,36 @@ def pool_sweeps(s: np.ndarray, beta: float, seed: int, stream_id: int, t0: int, 
     if rc != 0:
         raise ValueError("bad pool size")
     return EM
+
+
+def pool_window(L, beta, seed, stream_id, init_kind, t0, n, m, linear, x0, y0, w, h,
+                pool=None) -> np.ndarray:
+    """Exact w x h window at (x0, y0) after n sweeps (from sweep counter t0,
+    fresh init) of the pattern-pool dynamics, by the light cone.  pool: the
+    (exp4, exp8) arrays of pool_fill for the same beta, seed and stream id
+    (filled here when None)."""
+    e4, e8 = pool if pool is not None else pool_fill(beta, seed, stream_id, m)
+    assert e4.dtype == np.uint64 and e8.dtype == np.uint64 and len(e4) == len(e8) == 1 << m
+    out = np.empty((h, w), dtype=np.int8)
+    pu64 = ctypes.POINTER(ctypes.c_uint64)
+    rc = lib().oracle_pool_window(L, seed, stream_id, init_kind, t0, n, m, 1 if linear else 0,
+                                  e4.ctypes.data_as(pu64), e8.ctypes.data_as(pu64), x0, y0, w,
+                                  h, _p8(out))
+    if rc != 0:
+        raise ValueError("window plus light-cone margin does not fit in the lattice")
+    return out
+
+
+def lcg_window(L, beta, seed, stream_id, init_kind, n, x0, y0, w, h) -> np.ndarray:
+    """Exact w x h window at (x0, y0) after n sweeps of the per-thread-LCG
+    dynamics from a fresh init and the thread seeds of lcg_seed(L, seed)."""
+    t4, t8 = lcg_thresholds(beta)
+    out = np.empty((h, w), dtype=np.int8)
+    rc = lib().oracle_lcg_window(L, t4, t8, seed, stream_id, init_kind, n, x0, y0, w, h,
+                                 _p8(out))
+    if rc != 0:
+        raise ValueError("window plus light-cone margin does not fit in the lattice")
+    return out
 
 
 def set_threads(n: int) -> None:

@@ -570,6 +570,181 @@ int oracle_band_em(int64_t L, uint32_t t4, uint32_t t8, uint64_t seed, uint32_t 
     return 0;
 }
 
+/* ------------------------------------------------------------------ */
+/* Light-cone windows of the two alternative dynamics.  The argument of */
+/* oracle_window holds for them too: a site's update reads its four    */
+/* neighbours and a random decision that does not depend on any spin   */
+/* (a pool pattern at an address keyed by the global word index and    */
+/* the sweep, or the next draw of its word's generator), so after n     */
+/* sweeps the inner window of a patch with margin m = 2n + 1 (outer     */
+/* ring frozen) equals the whole lattice exactly.  Requires w + 2m <= L */
+/* and h + 2m <= L; 0 on success, -1 on a size or memory error.         */
+/* ------------------------------------------------------------------ */
+
+/* initial spins of the patch [x0 - m, x0 - m + pw) x [y0 - m, y0 - m + ph) */
+static void patch_init(int64_t L, uint64_t seed, uint32_t stream_id, int init, int64_t x0,
+                       int64_t y0, int64_t m, int64_t pw, int64_t ph, int8_t *p)
+{
+    for (int64_t j = 0; j < ph; ++j)
+        for (int64_t i = 0; i < pw; ++i) {
+            int64_t gx = wrap(x0 - m + i, L), gy = wrap(y0 - m + j, L);
+            int8_t v;
+            if (init == 0)
+                v = 1;
+            else if (init == 1)
+                v = -1;
+            else {
+                uint32_t colour = (uint32_t)((gx + gy) & 1);
+                uint32_t u = oracle_uniform(seed, stream_id, 2u + colour, 0u, L, gx, gy);
+                v = (u < 0x80000000u) ? 1 : -1;
+            }
+            p[j * pw + i] = v;
+        }
+}
+
+static int anti_aligned(const int8_t *p, int64_t pw, int64_t i, int64_t j)
+{
+    int v = p[j * pw + i];
+    return (p[j * pw + i - 1] != v) + (p[j * pw + i + 1] != v) + (p[(j - 1) * pw + i] != v) +
+           (p[(j + 1) * pw + i] != v);
+}
+
+/* Pattern-pool dynamics (see oracle_pool_sweeps): n sweeps from sweep     */
+/* counter t0 with the pool (e4, e8) of 2^m patterns.                     */
+int oracle_pool_window(int64_t L, uint64_t seed, uint32_t stream_id, int init, uint32_t t0,
+                       int64_t n, int m_pool, int linear, const uint64_t *e4,
+                       const uint64_t *e8, int64_t x0, int64_t y0, int64_t w, int64_t h,
+                       int8_t *out)
+{
+    int64_t m = 2 * n + 1;
+    int64_t pw = w + 2 * m, ph = h + 2 * m;
+    int64_t W = (L / 2 + 63) / 64;
+    if (pw > L || ph > L || w <= 0 || h <= 0 || m_pool < 1 || m_pool > 30)
+        return -1;
+    int8_t *p = (int8_t *)malloc((size_t)(pw * ph));
+    if (!p)
+        return -1;
+    patch_init(L, seed, stream_id, init, x0, y0, m, pw, ph, p);
+    for (int64_t k = 0; k < n; ++k) {
+        uint32_t t = t0 + (uint32_t)k;
+        for (int colour = 0; colour < 2; ++colour) {
+            for (int64_t j = 1; j < ph - 1; ++j)
+                for (int64_t i = 1; i < pw - 1; ++i) {
+                    int64_t gx = wrap(x0 - m + i, L), gy = wrap(y0 - m + j, L);
+                    if (((gx + gy) & 1) != colour)
+                        continue;
+                    int64_t site = gx / 2;                /* colour-local index in the row */
+                    uint64_t word = (uint64_t)(gy * W + site / 64);
+                    uint32_t a = oracle_pool_address(seed, stream_id, t, colour, m_pool, linear,
+                                                     word);
+                    int exp8 = (int)((e8[a] >> (site % 64)) & 1u);
+                    int exp4 = (int)((e4[a] >> (site % 64)) & 1u);
+                    if (anti_aligned(p, pw, i, j) + 2 * exp8 + exp4 >= 2)  /* Eq. (5) */
+                        p[j * pw + i] = (int8_t)(-p[j * pw + i]);
+                }
+        }
+    }
+    for (int64_t j = 0; j < h; ++j)
+        memcpy(out + j * w, p + (j + m) * pw + m, (size_t)w);
+    free(p);
+    return 0;
+}
+
+/* 16807^e mod 2^32 by square and multiply (thread seeds of Eq. (7)). */
+static uint32_t pow16807(uint64_t e)
+{
+    uint32_t r = 1u, b = 16807u;
+    while (e) {
+        if (e & 1u)
+            r = (uint32_t)((uint64_t)r * b);
+        b = (uint32_t)((uint64_t)b * b);
+        e >>= 1;
+    }
+    return r;
+}
+
+/* Per-thread-LCG dynamics (see oracle_lcg_sweeps), n sweeps from the     */
+/* thread seeds of oracle_lcg_seed (sweep 0).  Every word a patch row     */
+/* touches keeps its own generator: state (colour L + y) W + w starts at  */
+/* seed 16807^((colour L + y) W + w) and makes its 64 draws per colour    */
+/* step whether or not its sites lie in the patch.                        */
+int oracle_lcg_window(int64_t L, uint32_t t4, uint32_t t8, uint64_t seed, uint32_t stream_id,
+                      int init, int64_t n, int64_t x0, int64_t y0, int64_t w, int64_t h,
+                      int8_t *out)
+{
+    int64_t m = 2 * n + 1;
+    int64_t pw = w + 2 * m, ph = h + 2 * m;
+    int64_t half = L / 2, W = (L / 2 + 63) / 64;
+    if (pw > L || ph > L || w <= 0 || h <= 0)
+        return -1;
+    int8_t *p = (int8_t *)malloc((size_t)(pw * ph));
+    /* words of each (colour, patch row): at most pw / 128 + 2 per row */
+    int64_t per = pw / 128 + 3;
+    int64_t *wid = (int64_t *)malloc((size_t)(2 * ph * per) * sizeof(int64_t));
+    uint32_t *st = (uint32_t *)malloc((size_t)(2 * ph * per) * sizeof(uint32_t));
+    int64_t *cnt = (int64_t *)calloc((size_t)(2 * ph), sizeof(int64_t));
+    if (!p || !wid || !st || !cnt) {
+        free(p);
+        free(wid);
+        free(st);
+        free(cnt);
+        return -1;
+    }
+    patch_init(L, seed, stream_id, init, x0, y0, m, pw, ph, p);
+    for (int colour = 0; colour < 2; ++colour)
+        for (int64_t j = 1; j < ph - 1; ++j) {
+            int64_t gy = wrap(y0 - m + j, L), r = colour * ph + j;
+            for (int64_t i = 1; i < pw - 1; ++i) {
+                int64_t gx = wrap(x0 - m + i, L);
+                if (((gx + gy) & 1) != colour)
+                    continue;
+                int64_t word = (gx / 2) / 64, seen = 0;
+                for (int64_t q = 0; q < cnt[r]; ++q)
+                    seen |= wid[r * per + q] == word;
+                if (!seen) {
+                    wid[r * per + cnt[r]] = word;
+                    st[r * per + cnt[r]] =
+                        (uint32_t)((uint64_t)(uint32_t)seed *
+                                   pow16807((uint64_t)((colour * L + gy) * W + word)));
+                    ++cnt[r];
+                }
+            }
+        }
+    for (int64_t k = 0; k < n; ++k)
+        for (int colour = 0; colour < 2; ++colour)
+            for (int64_t j = 1; j < ph - 1; ++j) {
+                int64_t gy = wrap(y0 - m + j, L), r = colour * ph + j;
+                for (int64_t q = 0; q < cnt[r]; ++q) {
+                    int64_t word = wid[r * per + q];
+                    uint32_t x = st[r * per + q];
+                    for (int d = 1; d <= 64; ++d) {
+                        x = (uint32_t)((uint64_t)1664525u * x + 1013904223u);
+                        int64_t site = 64 * word + 64 - d;
+                        if (site >= half)
+                            continue;
+                        int64_t gx = 2 * site + ((gy + colour) & 1);
+                        int64_t i = wrap(gx - (x0 - m), L);  /* patch column */
+                        if (i < 1 || i > pw - 2)
+                            continue;
+                        int32_t sx = (int32_t)x;
+                        uint32_t u = (uint32_t)(sx < 0 ? -(int64_t)sx : (int64_t)sx);
+                        int v = p[j * pw + i];
+                        if (oracle_accept(v, p[j * pw + i - 1], p[j * pw + i + 1],
+                                          p[(j - 1) * pw + i], p[(j + 1) * pw + i], u, t4, t8))
+                            p[j * pw + i] = (int8_t)(-v);
+                    }
+                    st[r * per + q] = x;
+                }
+            }
+    for (int64_t j = 0; j < h; ++j)
+        memcpy(out + j * w, p + (j + m) * pw + m, (size_t)w);
+    free(p);
+    free(wid);
+    free(st);
+    free(cnt);
+    return 0;
+}
+
 /* Number of OpenMP threads the oracle uses (1 when built without it). */
 int oracle_get_threads(void)
 {
