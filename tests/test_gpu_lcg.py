@@ -130,3 +130,32 @@ def test_benchmark_workload(I):
     assert np.array_equal(em, oem)
     assert np.array_equal(lat.get_spins(), s)
     assert np.array_equal(lat.lcg_states(), st)
+
+
+SPOTS = [(0, 0), (-20, -5), (-7, 100), (123456, -3), (0.5, 0.5), (-64, 777)]
+
+
+@pytest.mark.parametrize("L,T,n", [(262144, 2.0, 3), (100008, 2.269185, 2)])
+def test_large_lattices_in_light_cone_windows(I, L, T, n):
+    """The HBM-resident 262144^2 lattice (where the LCG kernel is profiled)
+    and 100008^2 (782 words per row, the last one partial) with the LCG
+    dynamics from a hot start: windows at the periodic corners, edges and
+    centre equal the oracle's light-cone windows of the same dynamics; every
+    (E, M) obeys the invariants and the last equals a recount."""
+    import torch
+    seed = 7
+    _say("case L=%d lcg, %d sweeps" % (L, n))
+    lat = _lcg_lattice(I, L, seed, workloads.INIT_HOT, 1.0 / T)
+    EM = lat.sweep_em(n).cpu().numpy()
+    N = L * L
+    assert np.all(EM[:, 0] % 4 == 0) and np.all((EM[:, 1] - N) % 2 == 0)
+    assert np.all(np.abs(EM[:, 0]) <= 2 * N) and np.all(np.abs(EM[:, 1]) <= N)
+    assert lat.measure() == (int(EM[-1, 0]), int(EM[-1, 1]))
+    for (sx, sy) in SPOTS:
+        x0 = int(sx * L) % L if isinstance(sx, float) else sx % L
+        y0 = int(sy * L) % L if isinstance(sy, float) else sy % L
+        got = lat.get_window(x0, y0, 40, 12)
+        want = oracle.lcg_window(L, 1.0 / T, seed, 0, workloads.INIT_HOT, n, x0, y0, 40, 12)
+        assert np.array_equal(got, want), (L, x0, y0)
+    del lat
+    torch.cuda.empty_cache()

@@ -142,3 +142,38 @@ def test_benchmark_workload(I, linear):
     oem = oracle.pool_sweeps(s, 1.0 / w.T, w.seed, w.stream_id, 0, n, m, linear)
     assert np.array_equal(em, oem)
     assert np.array_equal(lat.get_spins(), s)
+
+
+SPOTS = [(0, 0), (-20, -5), (-7, 100), (123456, -3), (0.5, 0.5), (-64, 777)]
+
+
+@pytest.mark.parametrize("linear", [False, True])
+@pytest.mark.parametrize("L,T,n", [(262144, 2.0, 3), (100008, 2.269185, 2)])
+def test_large_lattices_in_light_cone_windows(I, L, T, n, linear):
+    """The HBM-resident 262144^2 lattice (where the pool kernels are
+    profiled) and 100008^2 (782 words per row, the last one partial) with the
+    benchmark's pool of 2^22 patterns, both address rules, from a hot start:
+    windows at the periodic corners, edges and centre equal the oracle's
+    light-cone windows of the same dynamics; every (E, M) obeys the
+    invariants and the last equals a recount."""
+    import torch
+    seed, m = 7, 22
+    beta = 1.0 / T
+    _say("case L=%d pool m=%d linear=%s, %d sweeps" % (L, m, linear, n))
+    lat = I.Lattice(L, seed=seed, stream_id=0, init=workloads.INIT_HOT, beta=beta)
+    lat.use_pool(m, linear)
+    EM = lat.sweep_em(n).cpu().numpy()
+    N = L * L
+    assert np.all(EM[:, 0] % 4 == 0) and np.all((EM[:, 1] - N) % 2 == 0)
+    assert np.all(np.abs(EM[:, 0]) <= 2 * N) and np.all(np.abs(EM[:, 1]) <= N)
+    assert lat.measure() == (int(EM[-1, 0]), int(EM[-1, 1]))
+    pool = oracle.pool_fill(beta, seed, 0, m)
+    for (sx, sy) in SPOTS:
+        x0 = int(sx * L) % L if isinstance(sx, float) else sx % L
+        y0 = int(sy * L) % L if isinstance(sy, float) else sy % L
+        got = lat.get_window(x0, y0, 40, 12)
+        want = oracle.pool_window(L, beta, seed, 0, workloads.INIT_HOT, 0, n, m, linear, x0, y0,
+                                  40, 12, pool=pool)
+        assert np.array_equal(got, want), (L, linear, x0, y0)
+    del lat
+    torch.cuda.empty_cache()
