@@ -3,8 +3,10 @@ section 6), run together on one GPU with the in-process halo exchange:
 they must reproduce the whole lattice's spins and per-sweep (E, M) bit for
 bit, for even and uneven splits, one strip (its own halos), and at the real
 share shape of 262144^2 over 8 GPUs (eight strips of 32768 rows, compared
-on the device with the plain 262144^2 run and, in light-cone windows that
-straddle strip borders and the periodic wrap, with the oracle)."""
+on the device with the plain 262144^2 run, with the oracle's whole-lattice
+(E, M) of tests/golden/huge_em.txt, and in light-cone windows that straddle
+strip borders and the periodic wrap with the oracle)."""
+import os
 import sys
 
 import numpy as np
@@ -80,6 +82,19 @@ def _strip_window(torch, st, L, x0, y0, ww, hh):
     return out
 
 
+def _golden_em(L, T, seed, sid, init):
+    """{sweep: (E, M)} of the oracle's whole-lattice values for this lattice."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "huge_em.txt")
+    out = {}
+    for line in open(path):
+        f = line.split()
+        if not f or f[0].startswith("#"):
+            continue
+        if (int(f[0]), float(f[1]), int(f[2]), int(f[3]), int(f[4])) == (L, T, seed, sid, init):
+            out[int(f[5])] = (int(f[6]), int(f[7]))
+    return out
+
+
 def test_real_share_shape(I):
     """262144^2 split over 8 GPUs: eight 32768-row strips (1 GiB each)."""
     import torch
@@ -93,6 +108,11 @@ def test_real_share_shape(I):
     lat = I.Lattice(L, seed=w.seed, stream_id=w.stream_id, init=w.init, beta=1.0 / w.T)
     ref = lat.sweep_em(n).cpu().numpy()
     assert np.array_equal(em, ref)
+    # and the oracle's whole-lattice values (band sums, tests/golden/huge_em.txt)
+    gold = _golden_em(L, w.T, w.seed, w.stream_id, w.init)
+    assert len(gold) >= n
+    for k in range(n):
+        assert (int(em[k, 0]), int(em[k, 1])) == gold[k + 1], k
     # windows across the borders of strips 0/1 and 4/5 and across the wrap 7/0
     R = L // G
     for (x0, y0) in [(1000, R - 6), (123456, 5 * R - 3), (L - 20, L - 6)]:
