@@ -7,12 +7,14 @@ directory, one line per case and sweep:
 
   huge_em.txt   - "L T seed stream_id init sweep E M"
 
-Cases (hot start):
+Cases (hot start unless noted):
   262144^2, T = 2.0 and 3.0, seed 7, sweeps 1..10 (the HBM-resident
       benchmark lattice: more than 2^32 sites, so every E/M sum passes 32 bits)
   185368^2, T = 2.269185, seed 11, sweeps 1..4 (L not a power of two; more
       than 2^32 Philox blocks per colour)
   1048576^2, T = 2.0, seed 7, sweep 1 (2^33 words per colour plane)
+  65536^2, T = 2.0, seed 3, stream id 1, cold +1 start, sweeps 1..2 (2^32
+      up spins at the start: the batched path's 64-bit lattice totals)
 A case already present in the file is skipped, so the script resumes.
 
 Run:  python tests/golden/make_huge_em.py [threads] [max_L]
@@ -28,13 +30,14 @@ sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 import oracle  # noqa: E402
 
 OUT = os.path.join(HERE, "huge_em.txt")
-HOT = 2
-# (L, T, seed, stream_id, sweeps, band rows)
+HOT, COLD_UP = 2, 0
+# (L, T, seed, stream_id, init, sweeps, band rows)
 CASES = [
-    (262144, 2.0, 7, 0, 10, 2048),
-    (262144, 3.0, 7, 0, 10, 2048),
-    (185368, 2.269185, 11, 0, 4, 2048),
-    (1048576, 2.0, 7, 0, 1, 1024),
+    (262144, 2.0, 7, 0, HOT, 10, 2048),
+    (262144, 3.0, 7, 0, HOT, 10, 2048),
+    (185368, 2.269185, 11, 0, HOT, 4, 2048),
+    (1048576, 2.0, 7, 0, HOT, 1, 1024),
+    (65536, 2.0, 3, 1, COLD_UP, 2, 4096),
 ]
 
 
@@ -59,10 +62,10 @@ def main():
             f.write("# whole-lattice oracle E and M after each sweep, summed over bands of rows\n")
             f.write("# L T seed stream_id init sweep E M\n")
     have = _done()
-    for (L, T, seed, sid, n, band) in CASES:
+    for (L, T, seed, sid, init, n, band) in CASES:
         if max_L is not None and L > max_L:
             continue
-        if (L, T, seed, sid, HOT) in have:
+        if (L, T, seed, sid, init) in have:
             print("L=%d T=%r: already written" % (L, T), flush=True)
             continue
         t0 = time.time()
@@ -71,11 +74,11 @@ def main():
             if y % (16 * band) == 0 or y == L:
                 print("L=%d: %d of %d rows, %.0f s" % (L, y, L, time.time() - t0), flush=True)
 
-        EM = oracle.lattice_em_by_bands(L, 1.0 / T, seed, sid, HOT, n, band, progress)
+        EM = oracle.lattice_em_by_bands(L, 1.0 / T, seed, sid, init, n, band, progress)
         with open(OUT, "a") as f:
             for k in range(n):
                 f.write("%d %r %d %d %d %d %d %d\n"
-                        % (L, T, seed, sid, HOT, k + 1, int(EM[k, 0]), int(EM[k, 1])))
+                        % (L, T, seed, sid, init, k + 1, int(EM[k, 0]), int(EM[k, 1])))
         print("L=%d T=%r done in %.0f s" % (L, T, time.time() - t0), flush=True)
 
 
