@@ -143,11 +143,26 @@ def test_batched_rows_of_62_to_64_words(I, form):
     _batched_vs_plain(I, specs, 2, form=form)
 
 
+def _huge_golden(key):
+    """{sweep: (E, M)} of tests/golden/huge_em.txt for (L, T, seed, sid, init)."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "huge_em.txt")
+    out = {}
+    for line in open(path):
+        f = line.split()
+        if not f or f[0].startswith("#"):
+            continue
+        if (int(f[0]), float(f[1]), int(f[2]), int(f[3]), int(f[4])) == key:
+            out[int(f[5])] = (int(f[6]), int(f[7]))
+    return out
+
+
 def test_lattice_totals_past_2_to_the_32(I):
     """L = 65536 from a cold start: N = 2^32 up spins, so the per-lattice
     up-spin and bond totals of the fused finaliser need 64 bits.  Batched
-    per-sweep E/M equal the plain path's (64-bit per-block partials); spins
-    compared on windows (the full lattice is 4 GiB as int8)."""
+    per-sweep E/M equal the plain path's (64-bit per-block partials) and the
+    oracle's whole-lattice values (tests/golden/huge_em.txt); spins are
+    compared with the plain path and the oracle in light-cone windows (the
+    full lattice is 4 GiB as int8)."""
     import torch
     L, n = 65536, 2
     spec = [(L, 2.0, 3, 1, workloads.INIT_COLD_UP)]
@@ -159,9 +174,16 @@ def test_lattice_totals_past_2_to_the_32(I):
     p = _make(I, spec)[0]
     EMp = p.sweep_em(n).cpu().numpy()
     assert np.array_equal(EMb, EMp)
+    gold = _huge_golden((L, 2.0, 3, 1, workloads.INIT_COLD_UP))
+    assert sorted(gold) == [1, 2]
+    for k in range(n):
+        assert (int(EMb[k, 0]), int(EMb[k, 1])) == gold[k + 1], k
     assert EMp[-1, 1] > (1 << 31)  # most spins still up: the total exceeds 2^32 / 2
     for (x0, y0) in [(0, 0), (L - 40, L - 7), (L // 2, 12345)]:
-        assert np.array_equal(b.get_window(x0, y0, 64, 16), p.get_window(x0, y0, 64, 16))
+        got = b.get_window(x0, y0, 64, 16)
+        assert np.array_equal(got, p.get_window(x0, y0, 64, 16))
+        want = oracle.window(L, 0.5, 3, 1, workloads.INIT_COLD_UP, 0, n, x0, y0, 64, 16)
+        assert np.array_equal(got, want), (x0, y0)
 
 
 def _grid_golden():
