@@ -1,8 +1,11 @@
 """Autotuner: it measures and installs a shape, and every tile and strip
-shape gives bit-identical results (spins and per-sweep E/M)."""
+shape gives bit-identical results (spins and per-sweep E/M), and the
+default shape's run equals the oracle's (whole lattice up to 10008^2,
+light-cone windows above)."""
 import numpy as np
 import pytest
 
+import oracle
 import workloads
 
 pytestmark = pytest.mark.gpu
@@ -19,12 +22,30 @@ def I():
     ising.tuning_clear()
 
 
+def _against_oracle(em, spins, L, beta, seed, sid, init):
+    """The default shape's run (the reference every other shape is held
+    to) against the oracle: the whole lattice up to 10008^2, light-cone
+    windows at the corners, an edge and the centre above."""
+    n = len(em)
+    if L <= 10008:
+        s, oem = oracle.run(L, beta, seed, sid, init, n)
+        assert np.array_equal(em, oem)
+        assert np.array_equal(spins, s)
+        return
+    for (x0, y0) in [(0, 0), (L - 20, L - 5), (L - 7, 1000), (L // 2, L // 2)]:
+        want = oracle.window(L, beta, seed, sid, init, 0, n, x0, y0, 40, 12)
+        got = np.take(np.take(spins, np.arange(y0, y0 + 12) % L, axis=0),
+                      np.arange(x0, x0 + 40) % L, axis=1)
+        assert np.array_equal(got, want), (x0, y0)
+
+
 @pytest.mark.parametrize("L", [1024, 2056, 16384])
 def test_every_shape_is_bit_identical(I, L):
     I.tuning_clear()
     ref = I.Lattice(L, seed=3, stream_id=1, init=workloads.INIT_HOT, beta=1 / 2.3)
     ref_em = ref.sweep_em(6).cpu().numpy()
     ref_s = ref.get_spins()
+    _against_oracle(ref_em, ref_s, L, 1 / 2.3, 3, 1, workloads.INIT_HOT)
     for rpw in (1, 2, 4):
         for mb in (512, 2048):
             I.tuning_set([{"L_min": L, "L_max": L, "form": I.ISING_FORM_TILE, "rpw": rpw,
@@ -43,6 +64,7 @@ def test_strip_shapes_match_tiles(I, L):
     ref = I.Lattice(L, seed=5, stream_id=3, init=workloads.INIT_HOT, beta=1 / 2.25)
     ref_em = ref.sweep_em(5).cpu().numpy()
     ref_s = ref.get_spins()
+    _against_oracle(ref_em, ref_s, L, 1 / 2.25, 5, 3, workloads.INIT_HOT)
     # rows per task: the size rule, tails of 1..3 rows after the 4-row
     # unrolled cycle, and tasks longer than one resident wave's share
     for rows in (0, 1, 3, 4, 7, 64):
