@@ -106,7 +106,7 @@ def parse():
                         "instead of the batched autotuner's pick (profiling runs)")
     p.add_argument("--served-requests", type=int, default=2000,
                    help="requests of the 2000-request Poisson stream to serve (default: all, "
-                        "about 160 s)")
+                        "about 160 s; 0: only the capacity and plain-FIFO samples)")
     p.add_argument("--served-capacity", type=int, default=300,
                    help="requests of the stream queued at once to measure the server's capacity")
     p.add_argument("--served-arena-gib", type=float, default=1.0)
@@ -116,16 +116,9 @@ def parse():
     return p.parse_args()
 
 
-def bench_served(torch, ising, dev, n_req, arena_gib, quantum, plain_n, plain_rate, cap_n=300):
-    """Poisson stream of requests (L log-uniform in [32, 8192], T uniform in
-    [1.5, 3.5], sweeps log-uniform in [1e3, 1e5], seed 1000 + i, hot start)
-    served with continuous batching; arrival rate 0.7 x the plain throughput
-    divided by the mean work per request (1.30e11 spin updates).  Also the
-    server's capacity on the stream's first cap_n requests queued at once,
-    and the first plain_n requests run one at a time on the plain path."""
-    import numpy as np
-    rate = 0.7 * plain_rate * 1e9 / 1.30e11
-    stream = workloads.served_stream(2000, rate=rate)[:n_req]
+def _serve_stream(ising, dev, stream, arena_gib, quantum):
+    """Serve the requests at their scheduled arrival times; aggregate rate
+    and latencies."""
     srv = ising.Server(int(arena_gib * (1 << 30)), quantum_sweeps=quantum, device=dev)
     t0 = time.perf_counter()
     t0_abs = _monotonic_now()
@@ -166,21 +159,37 @@ def bench_served(torch, ising, dev, n_req, arena_gib, quantum, plain_n, plain_ra
     stats = srv.stats()
     srv.close()
     lat = np.array(lat)
-    out = {"value": round(work_done / (wall * 1e9), 2), "unit": "spin updates/ns",
-           "requests": len(stream), "rate_per_s": round(rate, 3),
-           "p50_latency_s": round(float(np.percentile(lat, 50)), 3),
-           "p99_latency_s": round(float(np.percentile(lat, 99)), 3),
-           "mean_latency_s": round(float(lat.mean()), 3),
-           "wall_s": round(wall, 3), "arena_gib": arena_gib, "quantum_sweeps": quantum,
-           "peak_arena_bytes": stats["peak_bytes"], "quanta": stats["quanta"],
-           "valu_roof_frac": round(work_done / (wall * 1e9) * ALU_OPS_PER_UPDATE * 1e9
-                                   / VALU_PEAK_LANE_OPS, 4)}
+    return {"value": round(work_done / (wall * 1e9), 2),
+            "p50_latency_s": round(float(np.percentile(lat, 50)), 3),
+            "p99_latency_s": round(float(np.percentile(lat, 99)), 3),
+            "mean_latency_s": round(float(lat.mean()), 3),
+            "wall_s": round(wall, 3),
+            "peak_arena_bytes": stats["peak_bytes"], "quanta": stats["quanta"],
+            "valu_roof_frac": round(work_done / (wall * 1e9) * ALU_OPS_PER_UPDATE * 1e9
+                                    / VALU_PEAK_LANE_OPS, 4)}
+
+
+def bench_served(torch, ising, dev, n_req, arena_gib, quantum, plain_n, plain_rate, cap_n=300):
+    """Poisson stream of requests (L log-uniform in [32, 8192], T uniform in
+    [1.5, 3.5], sweeps log-uniform in [1e3, 1e5], seed 1000 + i, hot start)
+    served with continuous batching; arrival rate 0.7 x the plain throughput
+    divided by the mean work per request (1.30e11 spin updates).  Also the
+    server's capacity on the stream's first cap_n requests queued at once,
+    and the first plain_n requests run one at a time on the plain path."""
+    import numpy as np
+    rate = 0.7 * plain_rate * 1e9 / 1.30e11
+    full = workloads.served_stream(2000, rate=rate)
+    stream = full[:n_req]
+    out = {"unit": "spin updates/ns", "requests": len(stream), "rate_per_s": round(rate, 3),
+           "arena_gib": arena_gib, "quantum_sweeps": quantum}
+    if stream:
+        out.update(_serve_stream(ising, dev, stream, arena_gib, quantum))
     # capacity: the first requests of the stream all queued at once, so the
     # server never waits for an arrival
     if cap_n > 0:
         print("bench: served capacity (%d requests queued at once)" % cap_n, file=sys.stderr,
               flush=True)
-        sub = stream[:cap_n]
+        sub = full[:cap_n]
         srv = ising.Server(int(arena_gib * (1 << 30)), quantum_sweeps=quantum, device=dev)
         reqs = [{"L": r.L, "beta": 1.0 / r.T, "seed": r.seed, "stream_id": r.stream_id,
                  "init": r.init, "n_sweeps": r.sweeps, "n_discard": r.sweeps // 5} for r in sub]
@@ -199,7 +208,7 @@ def bench_served(torch, ising, dev, n_req, arena_gib, quantum, plain_n, plain_ra
                                                    / VALU_PEAK_LANE_OPS, 4)}
     # the same requests one at a time through the plain path (FIFO, no overlap)
     if plain_n > 0:
-        sub = stream[:plain_n]
+        sub = full[:plain_n]
         tp = time.perf_counter()
         clock = 0.0
         plat = []
