@@ -67,6 +67,11 @@ def lib():
         L.oracle_lcg_window.argtypes = [i64, u32, u32, u64, u32, i32, i64, i64, i64, i64, i64,
                                         p8]
         L.oracle_lcg_window.restype = i32
+        L.oracle_pool_band_em.argtypes = [i64, u64, u32, i32, u32, i64, i32, i32, pu64, pu64,
+                                          i64, i64, p64]
+        L.oracle_pool_band_em.restype = i32
+        L.oracle_lcg_band_em.argtypes = [i64, u32, u32, u64, u32, i32, i64, i64, i64, p64]
+        L.oracle_lcg_band_em.restype = i32
         L.oracle_get_threads.argtypes = []
         L.oracle_get_threads.restype = i32
         L.oracle_set_threads.argtypes = [i32]
@@ -266,6 +271,32 @@ def lcg_window(L, beta, seed, stream_id, init_kind, n, x0, y0, w, h) -> np.ndarr
     if rc != 0:
         raise ValueError("window plus light-cone margin does not fit in the lattice")
     return out
+
+
+def lcg_band_em(L, beta, seed, stream_id, init_kind, n, y0, h) -> np.ndarray:
+    """Rows [y0, y0 + h)'s shares of (E, M) after each of n sweeps of the
+    per-thread-LCG dynamics (light cone over full rows): int64 [n, 2]."""
+    t4, t8 = lcg_thresholds(beta)
+    EM = np.zeros((n, 2), dtype=np.int64)
+    rc = lib().oracle_lcg_band_em(L, t4, t8, seed, stream_id, init_kind, n, y0, h, _p64(EM))
+    if rc != 0:
+        raise ValueError("band plus light-cone margin does not fit in the lattice")
+    return EM
+
+
+def pool_band_em(L, beta, seed, stream_id, init_kind, t0, n, m, linear, y0, h,
+                 pool=None) -> np.ndarray:
+    """Rows [y0, y0 + h)'s shares of (E, M) after each of n sweeps of the
+    pattern-pool dynamics (light cone over full rows): int64 [n, 2]."""
+    e4, e8 = pool if pool is not None else pool_fill(beta, seed, stream_id, m)
+    EM = np.zeros((n, 2), dtype=np.int64)
+    pu64 = ctypes.POINTER(ctypes.c_uint64)
+    rc = lib().oracle_pool_band_em(L, seed, stream_id, init_kind, t0, n, m, 1 if linear else 0,
+                                   e4.ctypes.data_as(pu64), e8.ctypes.data_as(pu64), y0, h,
+                                   _p64(EM))
+    if rc != 0:
+        raise ValueError("band plus light-cone margin does not fit in the lattice")
+    return EM
 
 
 def set_threads(n: int) -> None:

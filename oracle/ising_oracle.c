@@ -745,6 +745,147 @@ int oracle_lcg_window(int64_t L, uint32_t t4, uint32_t t8, uint64_t seed, uint32
     return 0;
 }
 
+/* ------------------------------------------------------------------ */
+/* Bands of rows for the two alternative dynamics: oracle_band_em's     */
+/* light-cone argument (a band with m = 2n + 1 extra rows above and     */
+/* below, outermost rows frozen, x periodic over the full width) with   */
+/* the LCG or pool decisions of oracle_lcg_window / oracle_pool_window. */
+/* EM[2k], EM[2k + 1] receive the rows [y0, y0 + h)'s shares of E      */
+/* (bonds to the right and downwards) and M after sweep k + 1.          */
+/* ------------------------------------------------------------------ */
+
+static int8_t *band_init(int64_t L, uint64_t seed, uint32_t stream_id, int init, int64_t y0,
+                         int64_t m, int64_t ph)
+{
+    int8_t *p = (int8_t *)malloc((size_t)(ph * L));
+    if (!p)
+        return NULL;
+#pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < ph; ++j) {
+        int64_t gy = wrap(y0 - m + j, L);
+        for (int64_t x = 0; x < L; ++x) {
+            int8_t v;
+            if (init == 0)
+                v = 1;
+            else if (init == 1)
+                v = -1;
+            else {
+                uint32_t colour = (uint32_t)((x + gy) & 1);
+                uint32_t u = oracle_uniform(seed, stream_id, 2u + colour, 0u, L, x, gy);
+                v = (u < 0x80000000u) ? 1 : -1;
+            }
+            p[j * L + x] = v;
+        }
+    }
+    return p;
+}
+
+static void band_measure(int64_t L, const int8_t *p, int64_t m, int64_t h, int64_t *E,
+                         int64_t *M)
+{
+    int64_t e = 0, s = 0;
+#pragma omp parallel for schedule(static) reduction(+ : e, s)
+    for (int64_t j = m; j < m + h; ++j)
+        for (int64_t x = 0; x < L; ++x) {
+            int64_t v = p[j * L + x];
+            e -= v * (p[j * L + wrap(x + 1, L)] + p[(j + 1) * L + x]);
+            s += v;
+        }
+    *E = e;
+    *M = s;
+}
+
+int oracle_pool_band_em(int64_t L, uint64_t seed, uint32_t stream_id, int init, uint32_t t0,
+                        int64_t n, int m_pool, int linear, const uint64_t *e4,
+                        const uint64_t *e8, int64_t y0, int64_t h, int64_t *EM)
+{
+    int64_t m = 2 * n + 1, ph = h + 2 * m, W = (L / 2 + 63) / 64;
+    if (ph > L || h <= 0 || n < 0 || L < 4 || (L & 1) || m_pool < 1 || m_pool > 30)
+        return -1;
+    int8_t *p = band_init(L, seed, stream_id, init, y0, m, ph);
+    if (!p)
+        return -1;
+    for (int64_t k = 0; k < n; ++k) {
+        uint32_t t = t0 + (uint32_t)k;
+        for (int colour = 0; colour < 2; ++colour) {
+#pragma omp parallel for schedule(static)
+            for (int64_t j = 1; j < ph - 1; ++j) {
+                int64_t gy = wrap(y0 - m + j, L);
+                for (int64_t x = (gy + colour) & 1; x < L; x += 2) {
+                    int64_t site = x / 2;
+                    uint64_t word = (uint64_t)(gy * W + site / 64);
+                    uint32_t a = oracle_pool_address(seed, stream_id, t, colour, m_pool, linear,
+                                                     word);
+                    int exp8 = (int)((e8[a] >> (site % 64)) & 1u);
+                    int exp4 = (int)((e4[a] >> (site % 64)) & 1u);
+                    int v = p[j * L + x];
+                    int anti = (p[j * L + wrap(x - 1, L)] != v) + (p[j * L + wrap(x + 1, L)] != v) +
+                               (p[(j - 1) * L + x] != v) + (p[(j + 1) * L + x] != v);
+                    if (anti + 2 * exp8 + exp4 >= 2)    /* Eq. (5) */
+                        p[j * L + x] = (int8_t)(-v);
+                }
+            }
+        }
+        band_measure(L, p, m, h, &EM[2 * k], &EM[2 * k + 1]);
+    }
+    free(p);
+    return 0;
+}
+
+int oracle_lcg_band_em(int64_t L, uint32_t t4, uint32_t t8, uint64_t seed, uint32_t stream_id,
+                       int init, int64_t n, int64_t y0, int64_t h, int64_t *EM)
+{
+    int64_t m = 2 * n + 1, ph = h + 2 * m;
+    int64_t half = L / 2, W = (L / 2 + 63) / 64;
+    if (ph > L || h <= 0 || n < 0 || L < 4 || (L & 1))
+        return -1;
+    int8_t *p = band_init(L, seed, stream_id, init, y0, m, ph);
+    uint32_t *st = (uint32_t *)malloc((size_t)(2 * ph * W) * sizeof(uint32_t));
+    if (!p || !st) {
+        free(p);
+        free(st);
+        return -1;
+    }
+    /* generator of word w of colour c in patch row j: thread (c L + gy) W + w */
+#pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < ph; ++j) {
+        int64_t gy = wrap(y0 - m + j, L);
+        for (int c = 0; c < 2; ++c)
+            for (int64_t w = 0; w < W; ++w)
+                st[(c * ph + j) * W + w] =
+                    (uint32_t)((uint64_t)(uint32_t)seed * pow16807((uint64_t)((c * L + gy) * W + w)));
+    }
+    for (int64_t k = 0; k < n; ++k) {
+        for (int colour = 0; colour < 2; ++colour) {
+#pragma omp parallel for schedule(static)
+            for (int64_t j = 1; j < ph - 1; ++j) {
+                int64_t gy = wrap(y0 - m + j, L);
+                for (int64_t w = 0; w < W; ++w) {
+                    uint32_t x = st[(colour * ph + j) * W + w];
+                    for (int d = 1; d <= 64; ++d) {
+                        x = (uint32_t)((uint64_t)1664525u * x + 1013904223u);
+                        int64_t site = 64 * w + 64 - d;
+                        if (site >= half)
+                            continue;
+                        int64_t px = 2 * site + ((gy + colour) & 1);
+                        int32_t sx = (int32_t)x;
+                        uint32_t u = (uint32_t)(sx < 0 ? -(int64_t)sx : (int64_t)sx);
+                        int v = p[j * L + px];
+                        if (oracle_accept(v, p[j * L + wrap(px - 1, L)], p[j * L + wrap(px + 1, L)],
+                                          p[(j - 1) * L + px], p[(j + 1) * L + px], u, t4, t8))
+                            p[j * L + px] = (int8_t)(-v);
+                    }
+                    st[(colour * ph + j) * W + w] = x;
+                }
+            }
+        }
+        band_measure(L, p, m, h, &EM[2 * k], &EM[2 * k + 1]);
+    }
+    free(p);
+    free(st);
+    return 0;
+}
+
 /* Number of OpenMP threads the oracle uses (1 when built without it). */
 int oracle_get_threads(void)
 {

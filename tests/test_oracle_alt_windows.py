@@ -80,3 +80,41 @@ def test_window_size_errors():
         oracle.lcg_window(16, 0.4, 1, 0, workloads.INIT_HOT, 3, 0, 0, 10, 4)  # 10 + 14 > 16
     with pytest.raises(ValueError):
         oracle.pool_window(16, 0.4, 1, 0, workloads.INIT_HOT, 0, 3, 4, False, 0, 0, 4, 10)
+
+
+def _bands(fn, L, rows):
+    total = None
+    for y0 in range(0, L, rows):
+        em = fn(y0, min(rows, L - y0))
+        total = em if total is None else total + em
+    return total
+
+
+@pytest.mark.parametrize("L,rows", [(136, 40), (264, 64), (256, 256 - 2 * 7)])
+@pytest.mark.parametrize("init", [workloads.INIT_HOT, workloads.INIT_COLD_DOWN])
+def test_lcg_bands_sum_to_the_whole_lattice(L, rows, init):
+    """Band sums of (E, M) with light-cone margins equal the whole-lattice
+    LCG oracle's per-sweep (E, M) (ragged and aligned L, a band of all but
+    the margins, and bands across the periodic wrap)."""
+    seed, sid, n, beta = 11, 2, 3, 1.0 / 2.269185
+    s = oracle.init(L, seed, sid, init)
+    want = oracle.lcg_sweeps(s, beta, oracle.lcg_seed(L, seed), n)
+    got = _bands(lambda y0, h: oracle.lcg_band_em(L, beta, seed, sid, init, n, y0, h), L, rows)
+    assert np.array_equal(got, want)
+    # a band that wraps: rows L - 20 .. L + 19 plus the rest
+    wrap = (oracle.lcg_band_em(L, beta, seed, sid, init, n, L - 20, 40) +
+            oracle.lcg_band_em(L, beta, seed, sid, init, n, 20, L - 40))
+    assert np.array_equal(wrap, want)
+
+
+@pytest.mark.parametrize("L,rows", [(136, 40), (264, 64)])
+@pytest.mark.parametrize("linear", [False, True])
+def test_pool_bands_sum_to_the_whole_lattice(L, rows, linear):
+    seed, sid, n, m, beta, t0 = 11, 2, 3, 8, 1.0 / 2.269185, 4
+    pool = oracle.pool_fill(beta, seed, sid, m)
+    for init in (workloads.INIT_HOT, workloads.INIT_COLD_UP):
+        s = oracle.init(L, seed, sid, init)
+        want = oracle.pool_sweeps(s, beta, seed, sid, t0, n, m, linear)
+        got = _bands(lambda y0, h: oracle.pool_band_em(L, beta, seed, sid, init, t0, n, m, linear,
+                                                       y0, h, pool=pool), L, rows)
+        assert np.array_equal(got, want), (init,)
