@@ -4,6 +4,7 @@ generator states, on ragged lattices (partial last words, one-word rows,
 W = 65), at several temperatures including beta = 0 and +inf; seeding;
 checkpoint/resume of spins and states; argument checks."""
 import math
+import os
 import sys
 
 import numpy as np
@@ -132,6 +133,22 @@ def test_benchmark_workload(I):
     assert np.array_equal(lat.lcg_states(), st)
 
 
+def _alt_golden(L, T, seed, sid, init, dyn):
+    """{sweep: (E, M)} of tests/golden/alt_em.txt (the oracle's band sums)."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "alt_em.txt")
+    out = {}
+    if not os.path.exists(path):
+        return out
+    for line in open(path):
+        f = line.split()
+        if not f or f[0].startswith("#"):
+            continue
+        if (int(f[0]), float(f[1]), int(f[2]), int(f[3]), int(f[4]), f[5]) == (L, T, seed, sid,
+                                                                             init, dyn):
+            out[int(f[6])] = (int(f[7]), int(f[8]))
+    return out
+
+
 SPOTS = [(0, 0), (-20, -5), (-7, 100), (123456, -3), (0.5, 0.5), (-64, 777)]
 
 
@@ -151,6 +168,11 @@ def test_large_lattices_in_light_cone_windows(I, L, T, n):
     assert np.all(EM[:, 0] % 4 == 0) and np.all((EM[:, 1] - N) % 2 == 0)
     assert np.all(np.abs(EM[:, 0]) <= 2 * N) and np.all(np.abs(EM[:, 1]) <= N)
     assert lat.measure() == (int(EM[-1, 0]), int(EM[-1, 1]))
+    gold = _alt_golden(L, T, seed, 0, workloads.INIT_HOT, "lcg")
+    if L == 262144:
+        assert sorted(gold) == list(range(1, n + 1)), "no oracle values for this case"
+    for k, (e, mm) in gold.items():
+        assert (int(EM[k - 1, 0]), int(EM[k - 1, 1])) == (e, mm), k
     for (sx, sy) in SPOTS:
         x0 = int(sx * L) % L if isinstance(sx, float) else sx % L
         y0 = int(sy * L) % L if isinstance(sy, float) else sy % L
