@@ -199,3 +199,39 @@ def test_large_lattices_in_light_cone_windows(I, L, T, n, linear):
         assert np.array_equal(got, want), (L, linear, x0, y0)
     del lat
     torch.cuda.empty_cache()
+
+
+def _large_alt(dyn):
+    """(E/M rows [2000, 2], {sweep: sha256}) of tests/golden/large_alt_*.txt."""
+    here = os.path.dirname(os.path.abspath(__file__))
+    em, sha = [], {}
+    for line in open(os.path.join(here, "golden", "large_alt_em.txt")):
+        f = line.split()
+        if f and not f[0].startswith("#") and f[0] == dyn:
+            em.append((int(f[2]), int(f[3])))
+    for line in open(os.path.join(here, "golden", "large_alt_sha256.txt")):
+        f = line.split()
+        if f and not f[0].startswith("#") and f[0] == dyn:
+            sha[int(f[1])] = f[2]
+    return np.array(em, dtype=np.int64), sha
+
+
+def test_benchmark_workload_all_sweeps(I):
+    """16384^2 from a cold start at T = 2.269185 with the benchmark's pool of
+    2^22 patterns at random addresses, all 2000 sweeps the benchmark times per
+    step: every (E, M) and the spin array at sweeps 1, 10 and 2000 (sha256)
+    against the oracle's stored values (tests/golden/make_large_alt.py)."""
+    import hashlib
+    ref_em, ref_sha = _large_alt("pool22")
+    w = workloads.LARGE
+    assert len(ref_em) == w.sweeps and sorted(ref_sha) == [1, 10, w.sweeps]
+    _say("case %s pool22, %d sweeps" % (w.name, w.sweeps))
+    lat = I.Lattice(w.L, seed=w.seed, stream_id=w.stream_id, init=w.init, beta=1.0 / w.T)
+    lat.use_pool(22, False)
+    done, ems = 0, []
+    for t in sorted(ref_sha):
+        ems.append(lat.sweep_em(t - done).cpu().numpy())
+        done = t
+        d = hashlib.sha256(np.ascontiguousarray(lat.get_spins()).tobytes()).hexdigest()
+        assert d == ref_sha[t], "spins differ after sweep %d" % t
+    assert np.array_equal(np.concatenate(ems, axis=0), ref_em)
